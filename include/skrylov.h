@@ -1,0 +1,191 @@
+/*
+ * skrylov.h -- C ABI of the MI355X (gfx950) sketched-and-truncated polynomial block
+ * Krylov solver for large sparse Sylvester equations
+ *
+ *        A X + X B = C1 C2^T,   A: n1 x n1, B: n2 x n2 sparse, C1: n1 x r, C2: n2 x r,
+ *
+ * after Palitta, Schweitzer and Simoncini, "Sketched and truncated polynomial Krylov
+ * subspace methods: matrix Sylvester equations" (arXiv 2311.16019), Algorithm 1 (s-PKSM).
+ *
+ * Conventions used by every entry point:
+ *   - Dense blocks ("n x r") are row-major FP64 arrays (element (i, c) at i*r + c).
+ *   - Pointers documented as "device" must point to memory allocated on the current
+ *     HIP device (hipMalloc, or a PyTorch CUDA tensor); "host" pointers to host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All device
+ *     work of a call is ordered on that stream; calls synchronise it only where stated.
+ *   - Return value: SKR_OK (0) or a positive status on success (results are valid),
+ *     a negative error code on failure (nothing was produced; skr_last_error() says why).
+ *   - The library never takes ownership of caller buffers; handles (skr_op, skr_result)
+ *     own their device memory until the matching *_destroy call.
+ *   - A handle may be used from one host thread at a time.
+ */
+#ifndef SKRYLOV_H
+#define SKRYLOV_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SKR_API __attribute__((visibility("default")))
+#else
+#define SKR_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct skr_op_s* skr_op;
+typedef struct skr_result_s* skr_result;
+
+enum {
+  SKR_OK = 0,
+  SKR_NOT_CONVERGED = 1, /* maxit reached; factors from the last projected solve      */
+  SKR_BREAKDOWN = 2,     /* a Krylov space became invariant; factors are valid          */
+  SKR_EINVAL = -1,       /* invalid argument (shape, parameter, pointer)                */
+  SKR_EHIP = -2,         /* a HIP runtime call failed                                   */
+  SKR_ENOMEM = -3,       /* device allocation failed                                    */
+  SKR_ENOTSUP = -4,      /* valid request this build does not support                   */
+  SKR_EPROJ = -5         /* projected Sylvester solve failed (see skr_last_error)       */
+};
+
+enum { SKR_FP64 = 0, SKR_MIXED = 1 };           /* bulk precision                       */
+enum { SKR_SKETCH_SPARSE_SIGN = 0 };            /* subspace embedding                   */
+enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
+
+/*
+ * Solver parameters (Algorithm 1's inputs plus this library's choices).
+ *   k         truncation: orthogonalise against the last k blocks (eqn:arnoldi_tr), k >= 1
+ *   maxit     maximum number of block steps d
+ *   p         check period: the projected equation is solved when d % p == 0 and at maxit
+ *   s         sketch rows (s x n embeddings S_U, S_V); 0 means 2*maxit*r rounded up to a
+ *             multiple of zeta.  Requires s >= (maxit+1)*r and s % zeta == 0.
+ *   tol       relative stop test  rho <= tol * ||beta_1 beta_2^T||_F  (eq:resnorm_sk with
+ *             the whitened subdiagonal blocks)
+ *   seed      embedding seed; S_U uses seed, S_V uses splitmix64_mix(seed + 1)
+ *   zeta      nonzeros per column of the sparse sign embedding (default 8)
+ *   precision SKR_FP64, or SKR_MIXED (FP32 sparse products, orthogonalisation and sketch
+ *             input; FP64 sketched quantities, projected solve and residual estimate)
+ *   sketch    SKR_SKETCH_SPARSE_SIGN
+ *   recover   SKR_RECOVER_STORED (keep every basis block in HBM) or
+ *             SKR_RECOVER_TWO_PASS (keep k+1 blocks, regenerate them for the factors)
+ *   trunc_tol relative Frobenius cutoff of the low-rank factorisation of the projected
+ *             solution Y (0 keeps everything)
+ */
+typedef struct {
+  int32_t k;
+  int32_t maxit;
+  int32_t p;
+  int32_t zeta;
+  int64_t s;
+  double tol;
+  uint64_t seed;
+  int32_t precision;
+  int32_t sketch;
+  int32_t recover;
+  int32_t reserved0;
+  double trunc_tol;
+} skr_params;
+
+/* Fill *p with defaults: k=2, maxit=200, p=20, zeta=8, s=0, tol=1e-6, seed=0,
+ * SKR_FP64, sparse sign, stored basis, trunc_tol=1e-12.  Returns SKR_OK. */
+SKR_API int skr_params_default(skr_params* p);
+
+/*
+ * Create a sparse operator from a square CSR matrix M (n x n, nnz nonzeros).
+ *   rowptr  host int32[n+1], rowptr[0] = 0, nondecreasing, rowptr[n] = nnz
+ *   colind  host int32[nnz], each in [0, n)
+ *   vals    host FP64[nnz]
+ *   diag    host FP64[n] or NULL: an extra diagonal term, the operator is M + diag(diag)
+ * The library copies the matrix to the device, builds the CSR of M^T (needed for the
+ * Krylov space of B^T and for adjoint solves) and FP32 copies of both for mixed
+ * precision.  Synchronises `stream` before returning.  Errors: SKR_EINVAL for a
+ * malformed CSR (checked on the host), SKR_ENOMEM, SKR_EHIP.
+ */
+SKR_API int skr_op_create_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                      const double* vals, const double* diag, void* stream, skr_op* out);
+
+/* Replace the diagonal term: diag is a device FP64[n] pointer (copied, stream-ordered)
+ * or NULL to remove it.  Used to differentiate with respect to a reaction term. */
+SKR_API int skr_op_set_diag(skr_op op, const double* diag, void* stream);
+
+/* Size of the operator. */
+SKR_API int skr_op_size(skr_op op, int64_t* n, int64_t* nnz);
+
+SKR_API int skr_op_destroy(skr_op op);
+
+/*
+ * Solve A X + X B = C1 C2^T (Algorithm 1): Krylov spaces K(A, C1) and K(B^T, C2).
+ *   C1  device FP64 n1 x r row-major,  C2  device FP64 n2 x r row-major,  1 <= r <= 16
+ * On success *out holds X ~ X1 X2^T with X1: n1 x ell, X2: n2 x ell (ell <= d*r).
+ * The call is stream-ordered on `stream` and synchronises it once per residual check
+ * (reading rho) and at the end.  Returns SKR_OK, SKR_NOT_CONVERGED or SKR_BREAKDOWN
+ * with valid factors, or a negative error.
+ */
+SKR_API int skr_solve(skr_op A, skr_op B, const double* C1, const double* C2, int64_t r,
+              const skr_params* params, void* stream, skr_result* out);
+
+/*
+ * Solve the transposed equation A^T L + L B^T = G1 G2^T with the same method
+ * (Krylov spaces K(A^T, G1) and K(B, G2)); arguments as for skr_solve.  Its factors
+ * L ~ L1 L2^T give the gradient of a loss <G1 G2^T, X> with respect to the data of
+ * the forward equation.
+ */
+SKR_API int skr_adjoint_solve(skr_op A, skr_op B, const double* G1, const double* G2, int64_t r,
+                      const skr_params* params, void* stream, skr_result* out);
+
+/* Scalars of a result: rank ell of the factors, block steps d, last relative residual
+ * estimate rho/||beta_1 beta_2^T||_F, and the status returned by the solve. */
+SKR_API int skr_result_info(skr_result res, int64_t* ell, int32_t* iters, double* rho_rel, int32_t* status);
+
+/* Copy up to `cap` residual-history entries (block step, relative estimate) to host
+ * arrays; *len receives the number of entries available. */
+SKR_API int skr_result_history(skr_result res, int32_t* d, double* rho_rel, int32_t cap, int32_t* len);
+
+/* Copy the factors into caller buffers: X1 device FP64 n1 x ell, X2 device FP64
+ * n2 x ell, row-major (ell from skr_result_info).  Stream-ordered, no sync. */
+SKR_API int skr_result_copy_factors(skr_result res, double* X1, double* X2, void* stream);
+
+/* Device-time breakdown of the solve in milliseconds (HIP events): block steps,
+ * projected solves (incl. residual estimates), recovery.  Any pointer may be NULL. */
+SKR_API int skr_result_timing(skr_result res, double* ms_steps, double* ms_proj, double* ms_recover);
+
+SKR_API int skr_result_destroy(skr_result res);
+
+/*
+ * True relative residual ||A X + X B - C1 C2^T||_F / ||C1 C2^T||_F of X = X1 X2^T
+ * (the definition of the residual matrix in Sec. 3), evaluated on the device from the
+ * factors through QR factorisations of [A X1, X1, -C1] and [X2, B^T X2, C2].
+ * All matrices device FP64 row-major; X1 n1 x ell, X2 n2 x ell, C1 n1 x r, C2 n2 x r.
+ * Synchronises `stream`; result in *rel.
+ */
+SKR_API int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, int64_t ell,
+                      const double* C1, const double* C2, int64_t r, void* stream, double* rel);
+
+/*
+ * Loss and gradients of L = tr(P1^T X P2), X = X1 X2^T, given the adjoint factors
+ * Lam = L1 L2^T of A^T Lam + Lam B^T = P1 P2^T (dL = <Lam, dC1 C2^T + C1 dC2^T - dA X>):
+ *   dC1 = L1 (L2^T C2)   n1 x r        dC2 = L2 (L1^T C1)   n2 x r
+ *   dsig_i = -sum_j Lam_ij X_ij        n1   (gradient w.r.t. A's diagonal term)
+ *   dP1 = X1 (X2^T P2)   n1 x q        dP2 = X2 (X1^T P1)   n2 x q
+ * All arrays device FP64 row-major; ellx/elll are the factor ranks, q the columns of P.
+ * Any output pointer may be NULL to skip it.  *loss is written to host memory and the
+ * call synchronises `stream`.
+ */
+SKR_API int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q,
+                      const double* X1, const double* X2, int64_t ellx,
+                      const double* L1, const double* L2, int64_t elll,
+                      const double* C1, const double* C2, const double* P1, const double* P2,
+                      double* loss, double* dC1, double* dC2, double* dsig,
+                      double* dP1, double* dP2, void* stream);
+
+/* Thread-local message describing the last negative return on this thread. */
+SKR_API const char* skr_last_error(void);
+
+/* Library version string. */
+SKR_API const char* skr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKRYLOV_H */

@@ -1,0 +1,497 @@
+// FP64 dense kernels for the projected problems: tiled GEMM, blocked LU with partial
+// pivoting, triangular solves and the inverse built from them.
+#include <algorithm>
+#include <cmath>
+
+#include "dense.hpp"
+
+namespace skr {
+namespace dense {
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, GT = 256;
+
+// Element loaders: op(A)(i, k) and op(B)(k, j).  FAST selects the index that varies
+// fastest in memory so that tile loads are coalesced.
+struct LoadAN {  // A column-major, not transposed: fast in i
+  const double* A; int lda;
+  static constexpr bool I_FAST = true;
+  __device__ double operator()(int i, int k) const { return A[i + (size_t)k * lda]; }
+};
+struct LoadAT {  // A^T: fast in k
+  const double* A; int lda;
+  static constexpr bool I_FAST = false;
+  __device__ double operator()(int i, int k) const { return A[k + (size_t)i * lda]; }
+};
+struct LoadBN {  // B column-major, not transposed: fast in k
+  const double* B; int ldb;
+  static constexpr bool K_FAST = true;
+  __device__ double operator()(int k, int j) const { return B[k + (size_t)j * ldb]; }
+};
+struct LoadBT {  // B^T: fast in j
+  const double* B; int ldb;
+  static constexpr bool K_FAST = false;
+  __device__ double operator()(int k, int j) const { return B[j + (size_t)k * ldb]; }
+};
+template <typename T>
+struct LoadBasis {  // (i, q) -> U_{q / r}[i][q % r] for consecutive row-major n x r blocks
+  const T* U; int n, r;
+  static constexpr bool I_FAST = false;
+  __device__ double operator()(int i, int q) const {
+    const int j = q / r, c = q - j * r;
+    return static_cast<double>(U[((size_t)j * n + i) * r + c]);
+  }
+};
+struct StoreCM {  // column-major C
+  double* C; int ldc; double alpha, beta;
+  __device__ void operator()(int i, int j, double v) const {
+    double* p = C + i + (size_t)j * ldc;
+    *p = (beta == 0.0) ? alpha * v : alpha * v + beta * *p;
+  }
+};
+struct StoreRM {  // row-major C (element (i, j) at i*ldc + j)
+  double* C; int ldc; double alpha, beta;
+  __device__ void operator()(int i, int j, double v) const {
+    double* p = C + (size_t)i * ldc + j;
+    *p = (beta == 0.0) ? alpha * v : alpha * v + beta * *p;
+  }
+};
+
+template <class LA, class LB, class ST>
+__global__ void __launch_bounds__(GT) gemm_kernel(int m, int n, int k, LA la, LB lb, ST st) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k0 = 0; k0 < k; k0 += BK) {
+#pragma unroll
+    for (int e = tid; e < BM * BK; e += GT) {
+      int ii, kk;
+      if constexpr (LA::I_FAST) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < m && gk < k) ? la(gi, gk) : 0.0;
+    }
+#pragma unroll
+    for (int e = tid; e < BN * BK; e += GT) {
+      int jj, kk;
+      if constexpr (LB::K_FAST) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      Bs[kk][jj] = (gj < n && gk < k) ? lb(gk, gj) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = As[kk][tx + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Bs[kk][ty + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + tx + 16 * u, j = j0 + ty + 16 * v;
+      if (i < m && j < n) st(i, j, acc[u][v]);
+    }
+}
+
+template <class LA, class LB, class ST>
+void run_gemm(int m, int n, int k, LA la, LB lb, ST st, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  dim3 grid(ceil_div(m, BM), ceil_div(n, BN));
+  hipLaunchKernelGGL((gemm_kernel<LA, LB, ST>), grid, dim3(GT), 0, s, m, n, k, la, lb, st);
+  check_launch("gemm");
+}
+
+// ----------------------------------------------------------------------------- LU
+constexpr int NB = 32;     // LU / TRSM block size
+constexpr int PT = 1024;   // panel threads
+
+__global__ void __launch_bounds__(PT) panel_kernel(int n, double* A, int lda, int j0, int nb, int* ipiv, int* info) {
+  __shared__ double wval[PT / 64];
+  __shared__ int widx[PT / 64];
+  __shared__ int piv;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  for (int c = j0; c < j0 + nb; ++c) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = c + tid; i < n; i += PT) {
+      const double v = fabs(A[i + (size_t)c * lda]);
+      if (v > best) { best = v; bi = i; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { wval[wv] = best; widx[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = -1.0;
+      int ib = n;
+      for (int w = 0; w < PT / 64; ++w)
+        if (wval[w] > b || (wval[w] == b && widx[w] < ib)) { b = wval[w]; ib = widx[w]; }
+      if (ib >= n) ib = c;
+      piv = ib;
+      ipiv[c] = ib;
+      if (!(b > 0.0) && *info == 0) *info = c + 1;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != c)
+      for (int cc = j0 + tid; cc < j0 + nb; cc += PT) {
+        const double t = A[c + (size_t)cc * lda];
+        A[c + (size_t)cc * lda] = A[p + (size_t)cc * lda];
+        A[p + (size_t)cc * lda] = t;
+      }
+    __syncthreads();
+    const double pv = A[c + (size_t)c * lda];
+    if (pv != 0.0)
+      for (int i = c + 1 + tid; i < n; i += PT) A[i + (size_t)c * lda] /= pv;
+    __syncthreads();
+    const int rows = n - c - 1, cols = j0 + nb - c - 1;
+    if (rows > 0 && cols > 0)
+      for (int e = tid; e < rows * cols; e += PT) {
+        const int i = c + 1 + e % rows, cc = c + 1 + e / rows;
+        A[i + (size_t)cc * lda] -= A[i + (size_t)c * lda] * A[c + (size_t)cc * lda];
+      }
+    __syncthreads();
+  }
+}
+
+// Apply the panel's row interchanges to the columns outside [j0, j0+nb).
+__global__ void laswp_kernel(int n, double* A, int lda, int j0, int nb, const int* ipiv) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ncols = n - nb;
+  if (t >= ncols) return;
+  const int cc = t < j0 ? t : t + nb;
+  for (int c = j0; c < j0 + nb; ++c) {
+    const int p = ipiv[c];
+    if (p != c) {
+      const double x = A[c + (size_t)cc * lda];
+      A[c + (size_t)cc * lda] = A[p + (size_t)cc * lda];
+      A[p + (size_t)cc * lda] = x;
+    }
+  }
+}
+
+// B[r0:r0+nb, c0:c1) <- L^{-1} B with L the unit lower nb x nb block at (r0, r0) of L.
+__global__ void trsm_lln_diag_kernel(int nb, const double* L, int ldl, double* B, int ldb, int ncols) {
+  __shared__ double Ls[NB][NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Ls[e % nb][e / nb] = L[e % nb + (size_t)(e / nb) * ldl];
+  __syncthreads();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  double x[NB];
+  double* b = B + (size_t)col * ldb;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i < nb) {
+      double s = b[i];
+      for (int l = 0; l < i; ++l) s -= Ls[i][l] * x[l];
+      x[i] = s;
+      b[i] = s;
+    }
+  }
+}
+
+// B[r0:r0+nb, :] <- U^{-1} B with U the upper nb x nb block (non-unit).
+__global__ void trsm_lun_diag_kernel(int nb, const double* U, int ldu, double* B, int ldb, int ncols) {
+  __shared__ double Us[NB][NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Us[e % nb][e / nb] = U[e % nb + (size_t)(e / nb) * ldu];
+  __syncthreads();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  double x[NB];
+  double* b = B + (size_t)col * ldb;
+#pragma unroll
+  for (int ii = NB - 1; ii >= 0; --ii) {
+    if (ii < nb) {
+      double s = b[ii];
+#pragma unroll
+      for (int l = ii + 1; l < NB; ++l)
+        if (l < nb) s -= Us[ii][l] * x[l];
+      x[ii] = s / Us[ii][ii];
+      b[ii] = x[ii];
+    }
+  }
+}
+
+// B[:, c0:c0+nb] <- B T^{-1} with T the upper nb x nb diagonal block; one thread per row.
+__global__ void trsm_run_diag_kernel(int nb, const double* T, int ldt, double* B, int ldb, int nrows) {
+  __shared__ double Ts[NB][NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Ts[e % nb][e / nb] = T[e % nb + (size_t)(e / nb) * ldt];
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  double x[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < nb) {
+      double s = B[row + (size_t)c * ldb];
+      for (int l = 0; l < c; ++l) s -= x[l] * Ts[l][c];
+      x[c] = s / Ts[c][c];
+      B[row + (size_t)c * ldb] = x[c];
+    }
+  }
+}
+
+__global__ void logdet_kernel(int n, const double* A, int lda, double* out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += log(fabs(A[i + (size_t)i * lda]));
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) t += red[w];
+    *out = t;
+  }
+}
+
+__global__ void permuted_identity_kernel(int n, const int* ipiv, double* X, int ldx) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n) return;
+  double* x = X + (size_t)col * ldx;
+  for (int i = 0; i < n; ++i) x[i] = (i == col) ? 1.0 : 0.0;
+  for (int c = 0; c < n; ++c) {
+    const int p = ipiv[c];
+    if (p != c) { const double t = x[c]; x[c] = x[p]; x[p] = t; }
+  }
+}
+
+__global__ void copy_kernel(int m, int n, const double* A, int lda, double* B, int ldb) {
+  const size_t total = (size_t)m * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    B[i + (size_t)j * ldb] = A[i + (size_t)j * lda];
+  }
+}
+
+__global__ void transpose_kernel(int m, int n, const double* A, int lda, double* B, int ldb) {
+  __shared__ double tile[32][33];
+  const int bi = blockIdx.x * 32, bj = blockIdx.y * 32;
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int i = bi + threadIdx.x, j = bj + y;
+    if (i < m && j < n) tile[y][threadIdx.x] = A[i + (size_t)j * lda];
+  }
+  __syncthreads();
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int j = bj + threadIdx.x, i = bi + y;  // B(j, i) = A(i, j)
+    if (i < m && j < n) B[j + (size_t)i * ldb] = tile[threadIdx.x][y];
+  }
+}
+
+__global__ void zero_kernel(int m, int n, double* A, int lda) {
+  const size_t total = (size_t)m * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    A[e % m + (e / m) * (size_t)lda] = 0.0;
+}
+
+constexpr int RED_WG = 256, RED_MAXG = 1024;
+
+__global__ void combine_kernel(int m, int n, const double* mu_dev, const double* X, int ldx, const double* Y, int ldy,
+                               double* Z, int ldz, double* part) {
+  const double mu = *mu_dev;
+  const size_t total = (size_t)m * n;
+  double d2 = 0.0, z2 = 0.0, tr = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double x = X[i + (size_t)j * ldx];
+    const double z = 0.5 * (mu * x + Y[i + (size_t)j * ldy] / mu);
+    Z[i + (size_t)j * ldz] = z;
+    d2 += (z - x) * (z - x);
+    z2 += z * z;
+    if (i == j) tr += z;
+  }
+  __shared__ double red[3][RED_WG / 64];
+  d2 = wave_sum(d2); z2 = wave_sum(z2); tr = wave_sum(tr);
+  if (threadIdx.x % 64 == 0) { red[0][threadIdx.x / 64] = d2; red[1][threadIdx.x / 64] = z2; red[2][threadIdx.x / 64] = tr; }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int w = 0; w < RED_WG / 64; ++w) s += red[threadIdx.x][w];
+    part[threadIdx.x * RED_MAXG + blockIdx.x] = s;
+  }
+}
+
+__global__ void fro2_kernel(int m, int n, const double* A, int lda, double* part) {
+  const size_t total = (size_t)m * n;
+  double s2 = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const double a = A[e % m + (e / m) * (size_t)lda];
+    s2 += a * a;
+  }
+  __shared__ double red[RED_WG / 64];
+  s2 = wave_sum(s2);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < RED_WG / 64; ++w) s += red[w];
+    part[blockIdx.x] = s;
+  }
+}
+
+// Sum `ng` partials of each of `nq` quantities in a fixed order.
+__global__ void finalize_kernel(const double* part, int ng, int nq, double* o0, double* o1, double* o2) {
+  const int q = threadIdx.x;
+  if (q >= nq) return;
+  double s = 0.0;
+  for (int g = 0; g < ng; ++g) s += part[q * RED_MAXG + g];
+  double* o = q == 0 ? o0 : (q == 1 ? o1 : o2);
+  if (o) *o = s;
+}
+
+int red_grid(size_t total) { return (int)std::max<size_t>(1, std::min<size_t>(RED_MAXG, (total + RED_WG * 4 - 1) / (RED_WG * 4))); }
+
+}  // namespace
+
+int scratch_doubles() { return 3 * RED_MAXG; }
+
+void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+          double beta, double* C, int ldc, hipStream_t st) {
+  StoreCM sc{C, ldc, alpha, beta};
+  if (k <= 0) {  // C = beta C
+    if (beta == 0.0) set_zero(m, n, C, ldc, st);
+    else if (beta != 1.0) throw Error(SKR_ENOTSUP, "gemm with k = 0 and beta != 0, 1");
+    return;
+  }
+  if (!ta && !tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBN{B, ldb}, sc, st);
+  else if (ta && !tb) run_gemm(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, sc, st);
+  else if (!ta && tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, sc, st);
+  else run_gemm(m, n, k, LoadAT{A, lda}, LoadBT{B, ldb}, sc, st);
+}
+
+template <typename T>
+void basis_gemm(int n, int r, int nb, int l, double alpha, const T* U, const double* W, int ldw, double beta,
+                double* X, int ldx, hipStream_t st) {
+  run_gemm(n, l, nb * r, LoadBasis<T>{U, n, r}, LoadBN{W, ldw}, StoreRM{X, ldx, alpha, beta}, st);
+}
+template void basis_gemm<double>(int, int, int, int, double, const double*, const double*, int, double, double*, int,
+                                 hipStream_t);
+template void basis_gemm<float>(int, int, int, int, double, const float*, const double*, int, double, double*, int,
+                                hipStream_t);
+
+void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, hipStream_t st) {
+  SKR_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int nb = std::min(NB, n - j0);
+    hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(PT), 0, st, n, A, lda, j0, nb, ipiv, info);
+    check_launch("lu_panel");
+    if (n - nb > 0) {
+      hipLaunchKernelGGL(laswp_kernel, dim3(ceil_div(n - nb, 256)), dim3(256), 0, st, n, A, lda, j0, nb, ipiv);
+      check_launch("laswp");
+    }
+    const int rest = n - j0 - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(rest, 256)), dim3(256), 0, st, nb,
+                         A + j0 + (size_t)j0 * lda, lda, A + j0 + (size_t)(j0 + nb) * lda, lda, rest);
+      check_launch("lu_trsm");
+      gemm(false, false, rest, rest, nb, -1.0, A + (j0 + nb) + (size_t)j0 * lda, lda, A + j0 + (size_t)(j0 + nb) * lda,
+           lda, 1.0, A + (j0 + nb) + (size_t)(j0 + nb) * lda, lda, st);
+    }
+  }
+  if (logabsdet) {
+    hipLaunchKernelGGL(logdet_kernel, dim3(1), dim3(1024), 0, st, n, A, lda, logabsdet);
+    check_launch("logdet");
+  }
+}
+
+void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st) {
+  hipLaunchKernelGGL(permuted_identity_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, ipiv, X, ldx);
+  check_launch("permuted_identity");
+  // X <- L^{-1} X (unit lower, forward)
+  for (int b0 = 0; b0 < n; b0 += NB) {
+    const int nb = std::min(NB, n - b0);
+    hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, nb,
+                       LU + b0 + (size_t)b0 * lda, lda, X + b0, ldx, n);
+    check_launch("trsm_lln");
+    const int below = n - b0 - nb;
+    if (below > 0)
+      gemm(false, false, below, n, nb, -1.0, LU + (b0 + nb) + (size_t)b0 * lda, lda, X + b0, ldx, 1.0, X + b0 + nb,
+           ldx, st);
+  }
+  trsm_left_upper(n, n, LU, lda, X, ldx, st);
+}
+
+void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int nblk = ceil_div(n, NB);
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int b0 = bi * NB, nb = std::min(NB, n - b0);
+    hipLaunchKernelGGL(trsm_lun_diag_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, st, nb,
+                       T + b0 + (size_t)b0 * ldt, ldt, B + b0, ldb, nrhs);
+    check_launch("trsm_lun");
+    if (b0 > 0)
+      gemm(false, false, b0, nrhs, nb, -1.0, T + (size_t)b0 * ldt, ldt, B + b0, ldb, 1.0, B, ldb, st);
+  }
+}
+
+void trsm_right_upper(int m, int n, const double* T, int ldt, double* B, int ldb, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  for (int c0 = 0; c0 < n; c0 += NB) {
+    const int nb = std::min(NB, n - c0);
+    hipLaunchKernelGGL(trsm_run_diag_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, nb,
+                       T + c0 + (size_t)c0 * ldt, ldt, B + (size_t)c0 * ldb, ldb, m);
+    check_launch("trsm_run");
+    const int rest = n - c0 - nb;
+    if (rest > 0)
+      gemm(false, false, m, rest, nb, -1.0, B + (size_t)c0 * ldb, ldb, T + c0 + (size_t)(c0 + nb) * ldt, ldt, 1.0,
+           B + (size_t)(c0 + nb) * ldb, ldb, st);
+  }
+}
+
+void copy(int m, int n, const double* A, int lda, double* B, int ldb, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3(std::min(4096, ceil_div((int64_t)m * n, 256))), dim3(256), 0, st, m, n, A, lda,
+                     B, ldb);
+  check_launch("copy");
+}
+
+void transpose(int m, int n, const double* A, int lda, double* B, int ldb, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(transpose_kernel, dim3(ceil_div(m, 32), ceil_div(n, 32)), dim3(32, 8), 0, st, m, n, A, lda, B,
+                     ldb);
+  check_launch("transpose");
+}
+
+void set_zero(int m, int n, double* A, int lda, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(zero_kernel, dim3(std::min(4096, ceil_div((int64_t)m * n, 256))), dim3(256), 0, st, m, n, A, lda);
+  check_launch("zero");
+}
+
+void newton_combine(int m, int n, const double* mu_dev, const double* X, int ldx, const double* Y, int ldy, double* Z,
+                    int ldz, double* diff_dev, double* norm_dev, double* trace_dev, double* scratch, hipStream_t st) {
+  const int g = red_grid((size_t)m * n);
+  hipLaunchKernelGGL(combine_kernel, dim3(g), dim3(RED_WG), 0, st, m, n, mu_dev, X, ldx, Y, ldy, Z, ldz, scratch);
+  check_launch("newton_combine");
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, scratch, g, 3, diff_dev, norm_dev, trace_dev);
+  check_launch("finalize");
+}
+
+void fro2(int m, int n, const double* A, int lda, double* out, double* scratch, hipStream_t st) {
+  const int g = red_grid((size_t)m * n);
+  hipLaunchKernelGGL(fro2_kernel, dim3(g), dim3(RED_WG), 0, st, m, n, A, lda, scratch);
+  check_launch("fro2");
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, scratch, g, 1, out, nullptr, nullptr);
+  check_launch("finalize");
+}
+
+}  // namespace dense
+}  // namespace skr

@@ -1,0 +1,50 @@
+// FP64 dense linear algebra on the device for the small projected problems (sizes up to a
+// few thousand): tiled GEMM, blocked LU with partial pivoting, triangular solves, inverse.
+// All matrices are column-major with explicit leading dimensions.
+#pragma once
+
+#include "common.hpp"
+
+namespace skr {
+namespace dense {
+
+// C = alpha * op(A) op(B) + beta * C,  op(X) = X or X^T
+void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+          double beta, double* C, int ldc, hipStream_t st);
+
+// X1 (n x l, row-major, ld ldx) = alpha * sum_j U_j W[j r : (j+1) r, :] + beta * X1, where the
+// basis blocks U_j (n x r, row-major) are stored consecutively (block j at U + j n r) and W is
+// (nb r) x l column-major with leading dimension ldw.  T is the basis element type.
+template <typename T>
+void basis_gemm(int n, int r, int nb, int l, double alpha, const T* U, const double* W, int ldw, double beta,
+                double* X, int ldx, hipStream_t st);
+
+// In-place LU with partial pivoting of the n x n matrix A: P A = L U (unit L).  ipiv (device,
+// n entries) receives 0-based pivot rows; info (device int) is set to 1 + the first zero
+// pivot column if the matrix is exactly singular.  logabsdet (device double, may be null)
+// receives sum log|U_ii|.
+void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, hipStream_t st);
+
+// X = A^{-1} from the LU factors of getrf.  X is n x n with leading dimension ldx.
+void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st);
+
+// Solve T X = B in place (B <- T^{-1} B), T upper triangular n x n, B n x nrhs.
+void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st);
+// Solve X T = B in place (B <- B T^{-1}), T upper triangular n x n, B m x n.
+void trsm_right_upper(int m, int n, const double* T, int ldt, double* B, int ldb, hipStream_t st);
+
+// Elementwise helpers (column-major m x n views).
+void copy(int m, int n, const double* A, int lda, double* B, int ldb, hipStream_t st);
+void transpose(int m, int n, const double* A, int lda, double* B, int ldb, hipStream_t st);  // B = A^T
+void set_zero(int m, int n, double* A, int lda, hipStream_t st);
+// Z = (mu * X + Y / mu) / 2 with mu = *mu_dev; *diff_dev = ||Z - X||_F^2, *norm_dev = ||Z||_F^2,
+// *trace_dev = trace(Z) (square only, may be null).  Reductions are deterministic.
+void newton_combine(int m, int n, const double* mu_dev, const double* X, int ldx, const double* Y, int ldy, double* Z,
+                    int ldz, double* diff_dev, double* norm_dev, double* trace_dev, double* scratch, hipStream_t st);
+// *out = ||A||_F^2 (deterministic)
+void fro2(int m, int n, const double* A, int lda, double* out, double* scratch, hipStream_t st);
+
+int scratch_doubles();  // size of the `scratch` buffer the reductions need
+
+}  // namespace dense
+}  // namespace skr

@@ -1,0 +1,55 @@
+// Projected problem of s-PKSM on the device, FP64:
+//   M_A = T_{U,d+1} H_d T_{U,d}^{-1} (top dr rows; eqn:Hhat_Ghat), likewise M_B from G, T_V;
+//   solve M_A Y + Y M_B^T = E1 beta_1 beta_2^T E1^T (eqn:reduced_sk);
+//   rho = sqrt(||hhat E_d^T Y||_F^2 + ||Y E_d ghat^T||_F^2) (eq:resnorm_sk with the whitened
+//   subdiagonal blocks hhat = tau_{d+1} h_{d+1,d} tau_d^{-1});
+//   low-rank factors Y ~ Y1 Y2^T.
+#pragma once
+
+#include <string>
+
+#include "common.hpp"
+
+namespace skr {
+
+struct ProjSpace {
+  const double* H;   // column-major ((maxit+1) r) x (maxit r), leading dimension ld
+  const double* T;   // column-major ((maxit+1) r) square, leading dimension ld
+  int ld;
+  bool broken;       // subdiagonal block of the last column is zero
+};
+
+struct ProjStats {
+  int newton_iters = 0;
+  double proj_resid = 0.0;   // ||M_A Y + Y M_B^T - F||_F / ||F||_F
+  int neg_eigs_a = 0, neg_eigs_b = 0;
+};
+
+class ProjSolver {
+ public:
+  ProjSolver(int r, int mmax, hipStream_t st);
+  // Solve at block step d (m = d r).  F11 is the device r x r block beta_1 beta_2^T
+  // (row-major).  Returns rho (absolute).  Throws Error(SKR_EPROJ) when the projected
+  // equation cannot be solved by the sign iteration.
+  double solve(int d, const ProjSpace& u, const ProjSpace& v, const double* F11, ProjStats* stats);
+  // Low-rank factorisation of the last Y by Gaussian elimination with complete pivoting,
+  // stopped when ||Y - Y1 Y2^T||_F <= tol ||Y||_F.  Returns ell; Y1, Y2 are m x ell
+  // column-major with leading dimension m.
+  int factor(double tol);
+  const double* Y1() const { return y1_.p; }
+  const double* Y2() const { return y2_.p; }
+  int m() const { return m_; }
+  const double* Y() const { return c_.p; }
+
+ private:
+  void form(int d, const ProjSpace& sp, double* Mbar);
+  int r_, mmax_, m_ = 0;
+  hipStream_t st_;
+  DBuf<double> mbar_u_, mbar_v_, a_, b_, ai_, bi_, c_, w1_, w2_, lu_, y1_, y2_;
+  DBuf<int> ipiv_, info_;
+  DBuf<double> scal_, scratch_;
+  DBuf<double> acapart_;
+  DBuf<int> acaint_;
+};
+
+}  // namespace skr

@@ -1,0 +1,481 @@
+// Algorithm 1 (s-PKSM) driven from the host, all arithmetic on the device.
+//
+// Per block step d (both Krylov spaces in every launch):
+//   spmm_dot            U~ = Op U_d,  h_{i0,d} = U_{i0}^T U~          (i0 = max(1, d-k+1))
+//   axpy_reduce (k x)   U~ -= U_i h_{i,d}; next dot, or the Gram matrix of U~ at i = d
+//   gram2 (r > 1)       second Cholesky QR pass; h_{d+1,d} = R
+//   normalize           U_{d+1} = U~ R^{-1}
+//   sketch              w = S U_{d+1}
+//   whiten              Q_{d+1}, T_{d+1} (Prop. 2.1)
+// and, when d % p == 0 or d = maxit, the projected solve and the residual estimate
+// (one host synchronisation to read rho).  Finally the low-rank factors of Y and the
+// recovery X1 = U_d T_U^{-1} Y1, X2 = V_d T_V^{-1} Y2 from the stored basis or by
+// regenerating the basis from the stored Hessenberg blocks (two-pass).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <memory>
+
+#include "blockstep.hpp"
+#include "dense.hpp"
+#include "solver.hpp"
+#include "whiten.hpp"
+
+namespace skr {
+namespace {
+
+template <typename T>
+__global__ void convert_kernel(const double* src, T* dst, size_t count) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = static_cast<T>(src[e]);
+}
+
+__global__ void fill_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+// beta = T_1 ell for both spaces (T column-major with ld, ell column-major r x r);
+// F11 = beta_U beta_V^T (row-major).
+__global__ void rhs_block_kernel(int r, const double* TU, int ldu, const double* ellU, const double* TV, int ldv,
+                                 const double* ellV, double* F11) {
+  __shared__ double bu[RMAX * RMAX], bv[RMAX * RMAX];
+  const int e = threadIdx.x;
+  if (e < r * r) {
+    const int a = e / r, b = e % r;
+    double su = 0.0, sv = 0.0;
+    for (int c = 0; c < r; ++c) {
+      su += TU[a + (size_t)c * ldu] * ellU[c + (size_t)b * r];
+      sv += TV[a + (size_t)c * ldv] * ellV[c + (size_t)b * r];
+    }
+    bu[e] = su;
+    bv[e] = sv;
+  }
+  __syncthreads();
+  if (e < r * r) {
+    const int a = e / r, b = e % r;
+    double t = 0.0;
+    for (int c = 0; c < r; ++c) t += bu[a * r + c] * bv[b * r + c];
+    F11[e] = t;
+  }
+}
+
+// COEF <- h_{i,j} block of H (column-major), RFINV <- inverse of h_{j+1,j} (for replay)
+__global__ void replay_coef_kernel(int r, const double* Hblk, int ldh, double* small, int want_inv) {
+  if (threadIdx.x != 0) return;
+  double* coef = small + SmallLayout::COEF;
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) coef[a * r + b] = Hblk[a + (size_t)b * ldh];
+  if (want_inv) {
+    double* V = small + SmallLayout::RFINV;
+    for (int i = 0; i < r * r; ++i) V[i] = 0.0;
+    for (int j = 0; j < r; ++j) {
+      V[j * r + j] = 1.0 / coef[j * r + j];
+      for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k) s += coef[i * r + k] * V[k * r + j];
+        V[i * r + j] = -s / coef[i * r + i];
+      }
+    }
+  }
+}
+
+// COEF <- 0 (so that axpy_reduce with W = Y computes a plain Gram matrix)
+__global__ void zero_small_kernel(double* small, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) small[i] = 0.0;
+}
+
+int step_wgs(int n) {
+  int g = ceil_div(n, 4 * WG);
+  g = (g + 7) / 8 * 8;
+  return std::max(8, std::min(1024, g));
+}
+
+template <typename T>
+struct Space {
+  CsrView<T> A;
+  int n = 0, nwg = 0, nchunk = 0;
+  int nslots = 0;
+  bool stored = true;
+  DBuf<T> basis, work;
+  DBuf<double> H, Tm, Q, small, part, skpart, w, c1, c2, wpart, ell;
+  DBuf<unsigned> counter;
+  DBuf<int> broken;
+  DBuf<uint16_t> tab;
+  T* slot(int j) const {  // 1-based basis block j
+    const int idx = stored ? (j - 1) : ((j - 1) % nslots);
+    return basis.p + (size_t)idx * n * rr;
+  }
+  int rr = 0;
+};
+
+template <typename T>
+class Solver {
+ public:
+  Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
+      : r_(r), p_(p), st_(st) {
+    SKR_REQUIRE(r >= 1 && r <= RMAX, "r must be in [1, 16]");
+    SKR_REQUIRE(p.k >= 1, "k must be >= 1");
+    SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
+    SKR_REQUIRE(p.p >= 1, "p must be >= 1");
+    SKR_REQUIRE(p.zeta >= 1 && p.zeta <= 64, "zeta must be in [1, 64]");
+    SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN, "only the sparse sign embedding is supported");
+    SKR_REQUIRE(p.recover == SKR_RECOVER_STORED || p.recover == SKR_RECOVER_TWO_PASS, "invalid recovery mode");
+    SKR_REQUIRE(p.tol >= 0.0 && p.trunc_tol >= 0.0, "tolerances must be nonnegative");
+    s_ = p.s;
+    if (s_ == 0) {
+      s_ = 2 * (int64_t)p.maxit * r;
+      s_ = (s_ + p.zeta - 1) / p.zeta * p.zeta;
+    }
+    SKR_REQUIRE(s_ % p.zeta == 0, "s must be a multiple of zeta");
+    SKR_REQUIRE(s_ >= (int64_t)(p.maxit + 1) * r, "s must be at least (maxit+1) r");
+    SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
+    SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
+    ld_ = (p.maxit + 1) * r;
+    int dev = 0;
+    SKR_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SKR_HIP(hipGetDeviceProperties(&prop, dev));
+    lds_limit_ = std::max<size_t>(65536, prop.sharedMemPerBlock);
+    setup(sp_[0], A, tu);
+    setup(sp_[1], B, tv);
+  }
+
+  skr_result_s* run(const double* C1, const double* C2) {
+    std::unique_ptr<skr_result_s> res(new skr_result_s());
+    res->n1 = sp_[0].n;
+    res->n2 = sp_[1].n;
+    hipEvent_t e0, e1;
+    SKR_HIP(hipEventCreate(&e0));
+    SKR_HIP(hipEventCreate(&e1));
+    struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } eg{e0, e1};
+    SKR_HIP(hipEventRecord(e0, st_));
+    init(C1, C2);
+    double rhs = 0.0;
+    SKR_HIP(hipMemcpyAsync(&rhs_block_host_[0], F11_.p, sizeof(double) * r_ * r_, hipMemcpyDeviceToHost, st_));
+    int hb[2];
+    SKR_HIP(hipMemcpyAsync(&hb[0], sp_[0].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+    SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+    SKR_HIP(hipStreamSynchronize(st_));
+    if (hb[0] != INT_MAX || hb[1] != INT_MAX)
+      throw Error(SKR_EINVAL, "right-hand side factor is rank deficient or its sketch is singular");
+    for (int i = 0; i < r_ * r_; ++i) rhs += rhs_block_host_[i] * rhs_block_host_[i];
+    rhs = std::sqrt(rhs);
+    SKR_REQUIRE(rhs > 0.0 && std::isfinite(rhs), "zero or non-finite right-hand side");
+
+    ProjSolver proj(r_, p_.maxit * r_, st_);
+    int status = SKR_NOT_CONVERGED, dfinal = 0;
+    double rho_rel = 0.0;
+    for (int d = 1; d <= p_.maxit; ++d) {
+      block_step(d);
+      if (d % p_.p == 0 || d == p_.maxit) {
+        SKR_HIP(hipMemcpyAsync(&hb[0], sp_[0].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+        SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+        SKR_HIP(hipEventRecord(e1, st_));
+        SKR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        res->ms_steps += ms;
+        const int db = std::min(hb[0], hb[1]);
+        const int dc = std::min(d, db);
+        const bool broke = db <= d;
+        SKR_REQUIRE(dc >= 1, "breakdown in the first block step");
+        SKR_HIP(hipEventRecord(e0, st_));
+        ProjSpace pu{sp_[0].H.p, sp_[0].Tm.p, ld_, hb[0] == dc};
+        ProjSpace pv{sp_[1].H.p, sp_[1].Tm.p, ld_, hb[1] == dc};
+        const double rho = proj.solve(dc, pu, pv, F11_.p, &res->last_stats);
+        SKR_HIP(hipEventRecord(e1, st_));
+        SKR_HIP(hipEventSynchronize(e1));
+        SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        res->ms_proj += ms;
+        rho_rel = rho / rhs;
+        res->hist_d.push_back(dc);
+        res->hist_rho.push_back(rho_rel);
+        dfinal = dc;
+        SKR_HIP(hipEventRecord(e0, st_));
+        if (broke) { status = SKR_BREAKDOWN; break; }
+        if (rho_rel <= p_.tol) { status = SKR_OK; break; }
+      }
+    }
+    // factors and recovery
+    SKR_HIP(hipEventRecord(e0, st_));
+    const int m = dfinal * r_;
+    int ell = proj.factor(p_.trunc_tol);
+    DBuf<double> W1((size_t)m * ell), W2((size_t)m * ell);
+    dense::copy(m, ell, proj.Y1(), m, W1.p, m, st_);
+    dense::copy(m, ell, proj.Y2(), m, W2.p, m, st_);
+    dense::trsm_left_upper(m, ell, sp_[0].Tm.p, ld_, W1.p, m, st_);
+    dense::trsm_left_upper(m, ell, sp_[1].Tm.p, ld_, W2.p, m, st_);
+    res->X1.alloc((size_t)sp_[0].n * ell);
+    res->X2.alloc((size_t)sp_[1].n * ell);
+    if (p_.recover == SKR_RECOVER_STORED) {
+      dense::basis_gemm<T>(sp_[0].n, r_, dfinal, ell, 1.0, sp_[0].basis.p, W1.p, m, 0.0, res->X1.p, ell, st_);
+      dense::basis_gemm<T>(sp_[1].n, r_, dfinal, ell, 1.0, sp_[1].basis.p, W2.p, m, 0.0, res->X2.p, ell, st_);
+    } else {
+      replay(C1, C2, dfinal, ell, W1.p, W2.p, res->X1.p, res->X2.p);
+    }
+    SKR_HIP(hipEventRecord(e1, st_));
+    SKR_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    res->ms_recover = ms;
+    res->ell = ell;
+    res->iters = dfinal;
+    res->status = status;
+    res->rho_rel = rho_rel;
+    return res.release();
+  }
+
+ private:
+  void setup(Space<T>& s, const skr_op_s* op, int t) {
+    s.A = csr_view<T>(op, t);
+    s.n = (int)op->n;
+    s.rr = r_;
+    s.nwg = step_wgs(s.n);
+    s.stored = (p_.recover == SKR_RECOVER_STORED);
+    s.nslots = s.stored ? (p_.maxit + 1) : (p_.k + 1);
+    s.basis.alloc((size_t)s.nslots * s.n * r_);
+    s.work.alloc((size_t)s.n * r_);
+    s.H.alloc((size_t)ld_ * p_.maxit * r_);
+    s.Tm.alloc((size_t)ld_ * ld_);
+    s.Q.alloc((size_t)s_ * ld_);
+    s.small.alloc(SmallLayout::SIZE);
+    s.part.alloc((size_t)s.nwg * (RMAX * RMAX + 8));
+    s.counter.alloc(1);
+    s.broken.alloc(1);
+    s.nchunk = sketch_chunks(s.n);
+    s.skpart.alloc((size_t)s.nchunk * s_ * r_);
+    s.w.alloc((size_t)s_ * r_);
+    s.c1.alloc((size_t)ld_ * r_);
+    s.c2.alloc((size_t)ld_ * r_);
+    s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
+    s.ell.alloc((size_t)r_ * r_);
+    s.tab.alloc((size_t)s.n * p_.zeta);
+    s.H.zero(st_);
+    s.Tm.zero(st_);
+    s.small.zero(st_);
+    s.counter.zero(st_);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st_, s.broken.p, INT_MAX);
+    check_launch("fill_int");
+  }
+
+  SpaceStep<T> step_args(Space<T>& s, int d) {
+    SpaceStep<T> a{};
+    a.A = s.A;
+    a.Y = s.work.p;
+    a.small = s.small.p;
+    a.part = s.part.p;
+    a.counter = s.counter.p;
+    a.broken = s.broken.p;
+    a.ldh = ld_;
+    a.n = s.n;
+    a.nwg = s.nwg;
+    a.step = d;
+    return a;
+  }
+
+  double* Hblk(Space<T>& s, int i, int j) {  // 1-based block (i, j)
+    return s.H.p + (size_t)(i - 1) * r_ + (size_t)(j - 1) * r_ * ld_;
+  }
+
+  // Orthonormalise the start block: U_1 ell = C (Cholesky QR, twice for r > 1).
+  void start_block(Space<T>& s, const double* C, SpaceStep<T>& a) {
+    const size_t cnt = (size_t)s.n * r_;
+    hipLaunchKernelGGL(convert_kernel<T>, dim3(std::min<size_t>(4096, (cnt + 255) / 256)), dim3(256), 0, st_, C,
+                       s.work.p, cnt);
+    check_launch("convert");
+    hipLaunchKernelGGL(zero_small_kernel, dim3(1), dim3(256), 0, st_, s.small.p, (int)SmallLayout::SIZE);
+    check_launch("zero_small");
+    a.W = s.work.p;
+    a.Wn = nullptr;
+    a.post = POST_GRAM1;
+    a.Hblk = (r_ == 1) ? s.ell.p : nullptr;
+    a.ldh = r_;
+  }
+
+  void init(const double* C1, const double* C2) {
+    SpaceStep<T> a0 = step_args(sp_[0], 0), a1 = step_args(sp_[1], 0);
+    start_block(sp_[0], C1, a0);
+    start_block(sp_[1], C2, a1);
+    launch_axpy_reduce<T>(r_, a0, a1, st_);
+    if (r_ > 1) {
+      a0.post = a1.post = POST_GRAM2;
+      a0.Hblk = sp_[0].ell.p;
+      a1.Hblk = sp_[1].ell.p;
+      launch_gram2<T>(r_, a0, a1, st_);
+    }
+    a0.Unew = sp_[0].slot(1);
+    a1.Unew = sp_[1].slot(1);
+    launch_normalize<T>(r_, a0, a1, st_);
+    const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
+    for (int i = 0; i < 2; ++i)
+      launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
+    sketch(1);
+    whiten(0, 0);
+    F11_.alloc((size_t)r_ * r_);
+    hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p, sp_[1].Tm.p,
+                       ld_, sp_[1].ell.p, F11_.p);
+    check_launch("rhs_block");
+    rhs_block_host_.assign((size_t)r_ * r_, 0.0);
+  }
+
+  static uint64_t mix64_host(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+
+  void sketch(int j) {
+    SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].w.p, sp_[0].n, sp_[0].nchunk};
+    SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].w.p, sp_[1].n, sp_[1].nchunk};
+    launch_sketch<T>(r_, (int)s_, p_.zeta, k0, k1, lds_limit_, st_);
+  }
+
+  void whiten(int d, int step) {
+    WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].w.p, sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p, sp_[0].broken.p, ld_};
+    WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].w.p, sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p, sp_[1].broken.p, ld_};
+    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, st_);
+  }
+
+  void block_step(int d) {
+    const int i0 = std::max(1, d - p_.k + 1);
+    SpaceStep<T> a[2];
+    for (int q = 0; q < 2; ++q) {
+      Space<T>& s = sp_[q];
+      a[q] = step_args(s, d);
+      a[q].X = s.slot(d);
+      a[q].W = s.slot(i0);
+      a[q].post = POST_DOT;
+      a[q].Hblk = Hblk(s, i0, d);
+    }
+    launch_spmm_dot<T>(r_, a[0], a[1], st_);
+    for (int i = i0; i <= d; ++i) {
+      for (int q = 0; q < 2; ++q) {
+        Space<T>& s = sp_[q];
+        a[q].W = s.slot(i);
+        if (i < d) {
+          a[q].Wn = s.slot(i + 1);
+          a[q].post = POST_DOT;
+          a[q].Hblk = Hblk(s, i + 1, d);
+        } else {
+          a[q].Wn = nullptr;
+          a[q].post = POST_GRAM1;
+          a[q].Hblk = (r_ == 1) ? Hblk(s, d + 1, d) : nullptr;
+        }
+      }
+      launch_axpy_reduce<T>(r_, a[0], a[1], st_);
+    }
+    if (r_ > 1) {
+      for (int q = 0; q < 2; ++q) {
+        a[q].post = POST_GRAM2;
+        a[q].Hblk = Hblk(sp_[q], d + 1, d);
+      }
+      launch_gram2<T>(r_, a[0], a[1], st_);
+    }
+    for (int q = 0; q < 2; ++q) a[q].Unew = sp_[q].slot(d + 1);
+    launch_normalize<T>(r_, a[0], a[1], st_);
+    sketch(d + 1);
+    whiten(d, d);
+  }
+
+  // Two-pass recovery: regenerate U_1..U_d from C and the stored H (no inner products) and
+  // accumulate X += U_j W[j] in chunks of the ring buffer.
+  void replay(const double* C1, const double* C2, int d, int ell, const double* W1, const double* W2, double* X1,
+              double* X2) {
+    const double* Cs[2] = {C1, C2};
+    const double* Ws[2] = {W1, W2};
+    double* Xs[2] = {X1, X2};
+    // U_1 = C ell^{-1}: reuse the start-block kernels with R taken from ell
+    SpaceStep<T> a[2];
+    for (int q = 0; q < 2; ++q) {
+      Space<T>& s = sp_[q];
+      const size_t cnt = (size_t)s.n * r_;
+      hipLaunchKernelGGL(convert_kernel<T>, dim3(std::min<size_t>(4096, (cnt + 255) / 256)), dim3(256), 0, st_, Cs[q],
+                         s.work.p, cnt);
+      check_launch("convert");
+      hipLaunchKernelGGL(replay_coef_kernel, dim3(1), dim3(64), 0, st_, r_, s.ell.p, r_, s.small.p, 1);
+      check_launch("replay_coef");
+      a[q] = step_args(s, 0);
+      a[q].Unew = s.slot(1);
+    }
+    launch_normalize<T>(r_, a[0], a[1], st_);
+    // nslots = k + 1 in two-pass mode; accumulate a block into X before its ring slot is
+    // overwritten.
+    int flushed = 0;  // blocks 1..flushed have been accumulated into X
+    bool first = true;
+    auto flush = [&](int upto) {
+      // accumulate blocks flushed+1 .. upto (contiguous in the ring only when they do not wrap)
+      for (int j = flushed + 1; j <= upto; ++j) {
+        for (int q = 0; q < 2; ++q) {
+          Space<T>& s = sp_[q];
+          const int m = d * r_;
+          dense::basis_gemm<T>(s.n, r_, 1, ell, 1.0, s.slot(j), Ws[q] + (size_t)(j - 1) * r_, m, first ? 0.0 : 1.0,
+                               Xs[q], ell, st_);
+        }
+        first = false;
+      }
+      flushed = upto;
+    };
+    for (int j = 1; j < d; ++j) {
+      // before writing slot(j+1) the block j+1-nslots must have been flushed
+      const int evict = j + 1 - sp_[0].nslots;
+      if (evict >= 1 && flushed < evict) flush(evict);
+      for (int q = 0; q < 2; ++q) {
+        Space<T>& s = sp_[q];
+        a[q] = step_args(s, j);
+        a[q].X = s.slot(j);
+        a[q].W = s.slot(j);
+        a[q].post = POST_DOT;
+        a[q].Hblk = nullptr;
+      }
+      launch_spmm_dot<T>(r_, a[0], a[1], st_);
+      const int i0 = std::max(1, j - p_.k + 1);
+      for (int i = i0; i <= j; ++i) {
+        for (int q = 0; q < 2; ++q) {
+          Space<T>& s = sp_[q];
+          hipLaunchKernelGGL(replay_coef_kernel, dim3(1), dim3(64), 0, st_, r_, Hblk(s, i, j), ld_, s.small.p, 0);
+          check_launch("replay_coef");
+          a[q].W = s.slot(i);
+          a[q].Wn = s.slot(i);   // the dot result is discarded
+          a[q].post = POST_DOT;
+          a[q].Hblk = nullptr;
+        }
+        launch_axpy_reduce<T>(r_, a[0], a[1], st_);
+      }
+      for (int q = 0; q < 2; ++q) {
+        Space<T>& s = sp_[q];
+        hipLaunchKernelGGL(replay_coef_kernel, dim3(1), dim3(64), 0, st_, r_, Hblk(s, j + 1, j), ld_, s.small.p, 1);
+        check_launch("replay_coef");
+        a[q].Unew = s.slot(j + 1);
+      }
+      launch_normalize<T>(r_, a[0], a[1], st_);
+    }
+    flush(d);
+  }
+
+  int r_;
+  skr_params p_;
+  hipStream_t st_;
+  int64_t s_ = 0;
+  int ld_ = 0;
+  size_t lds_limit_ = 65536;
+  Space<T> sp_[2];
+  DBuf<double> F11_;
+  std::vector<double> rhs_block_host_;
+};
+
+}  // namespace
+
+skr_result_s* run_solve(const skr_op_s* A, int tu, const skr_op_s* B, int tv, const double* C1, const double* C2,
+                        int r, const skr_params& p, hipStream_t st) {
+  SKR_REQUIRE(A && B, "null operator");
+  SKR_REQUIRE(C1 && C2, "null right-hand side factor");
+  if (p.precision == SKR_FP64) {
+    Solver<double> s(A, tu, B, tv, r, p, st);
+    return s.run(C1, C2);
+  }
+  SKR_REQUIRE(p.precision == SKR_MIXED, "precision must be SKR_FP64 or SKR_MIXED");
+  Solver<float> s(A, tu, B, tv, r, p, st);
+  return s.run(C1, C2);
+}
+
+}  // namespace skr

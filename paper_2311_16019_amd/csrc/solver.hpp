@@ -1,0 +1,27 @@
+// Driver of Algorithm 1 (s-PKSM) on one GPU and the result object.
+#pragma once
+
+#include <vector>
+
+#include "op.hpp"
+#include "proj.hpp"
+
+struct skr_result_s {
+  int64_t n1 = 0, n2 = 0, ell = 0;
+  int32_t iters = 0, status = 0;
+  double rho_rel = 0.0;
+  std::vector<int32_t> hist_d;
+  std::vector<double> hist_rho;
+  skr::DBuf<double> X1, X2;  // row-major n x ell
+  double ms_steps = 0.0, ms_proj = 0.0, ms_recover = 0.0;
+  skr::ProjStats last_stats;
+};
+
+namespace skr {
+
+// Solve with Krylov spaces K(opU, C1) and K(opV, C2) where opU = A (transposed if tu)
+// and opV = B (transposed if tv).  The forward equation uses (A, tu=0) and (B, tv=1).
+skr_result_s* run_solve(const skr_op_s* A, int tu, const skr_op_s* B, int tv, const double* C1, const double* C2,
+                        int r, const skr_params& p, hipStream_t st);
+
+}  // namespace skr

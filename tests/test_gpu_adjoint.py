@@ -1,0 +1,86 @@
+"""GPU adjoint solve and gradients of L = tr(P1^T X P2) against the oracle's dense adjoint
+(exact at tiny sizes) and the oracle's s-PKSM adjoint, through the C ABI and the
+torch.autograd.Function."""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_ops, product_distance, to_dev, torch_cuda
+from oracle.adjoint import dense_grads, solve_and_grad
+from oracle.spksm import spksm as oracle_spksm
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(m=10, q=3):
+    cfg = make_config("reaction2d_500", m=m, r=2)
+    rng = np.random.Generator(np.random.PCG64(99))
+    P1 = rng.standard_normal((cfg["n"], q))
+    P2 = rng.standard_normal((cfg["n"], q))
+    return cfg, P1, P2
+
+
+def test_adjoint_solve_matches_oracle():
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=23, r=2)
+    rng = np.random.Generator(np.random.PCG64(5))
+    G1 = rng.standard_normal((cfg["n"], 2))
+    G2 = rng.standard_normal((cfg["n"], 2))
+    A, B = gpu_ops(cfg)
+    prm = dict(k=3, maxit=16, p=8, s=272, tol=0.0, seed=21)
+    g = skr.adjoint_solve(A, B, to_dev(G1), to_dev(G2), **prm)
+    At, Bt = cfg["A"].transpose(), cfg["B"].transpose()
+    o = oracle_spksm(At, Bt, G1, G2, **prm)
+    assert product_distance(g, o) <= 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_gradients_match_dense_adjoint(precision, tol):
+    import paper_2311_16019_amd as skr
+    cfg, P1, P2 = _case()
+    A, B = gpu_ops(cfg)
+    prm = dict(k=2, maxit=45, p=1, s=400, tol=1e-11 if precision == "fp64" else 1e-7, seed=4, precision=precision)
+    f = skr.solve(A, B, to_dev(cfg["C1"]), to_dev(cfg["C2"]), **prm)
+    a = skr.adjoint_solve(A, B, to_dev(P1), to_dev(P2), **prm)
+    gr = skr.pairing_grads(f.X1, f.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]), to_dev(P1), to_dev(P2), L1=a.X1, L2=a.X2)
+    ref = dense_grads(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], cfg["sigma"], P1, P2)
+    for key in ("dC1", "dC2", "dsig", "dP1", "dP2"):
+        refk = ref["dsigma" if key == "dsig" else key]
+        err = np.linalg.norm(gr[key].cpu().numpy() - refk) / np.linalg.norm(refk)
+        assert err <= tol, (key, err)
+    assert abs(gr["loss"] - ref["loss"]) <= tol * abs(ref["loss"])
+
+
+def test_autograd_function_matches_oracle_gradients():
+    import paper_2311_16019_amd as skr
+    torch = torch_cuda()
+    cfg, P1, P2 = _case(m=12)
+    prm = dict(k=2, maxit=60, p=2, s=496, tol=1e-10, seed=6)
+    A0, B = gpu_ops(dict(cfg, sigma=None))
+    C1 = to_dev(cfg["C1"]).requires_grad_(True)
+    C2 = to_dev(cfg["C2"]).requires_grad_(True)
+    sig = to_dev(cfg["sigma"]).requires_grad_(True)
+    tP1 = to_dev(P1).requires_grad_(True)
+    tP2 = to_dev(P2).requires_grad_(True)
+    L = skr.SylvesterPairing.apply(C1, C2, sig, tP1, tP2, A0, B, prm)
+    L.backward()
+    ref = solve_and_grad(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], cfg["sigma"], P1, P2, **prm)
+    dense = dense_grads(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], cfg["sigma"], P1, P2)
+    assert abs(L.item() - dense["loss"]) <= 1e-8 * abs(dense["loss"])
+    for t, key in ((C1, "dC1"), (C2, "dC2"), (sig, "dsigma"), (tP1, "dP1"), (tP2, "dP2")):
+        got = t.grad.cpu().numpy()
+        assert np.linalg.norm(got - ref[key]) <= 1e-6 * np.linalg.norm(ref[key]), key
+        assert np.linalg.norm(got - dense[key]) <= 1e-6 * np.linalg.norm(dense[key]), key
+
+
+def test_symmetric_adjoint_reproduces_forward():
+    """A, B symmetric and G = C1 C2^T: the adjoint solve is the forward solve."""
+    import paper_2311_16019_amd as skr
+    cfg = make_config("laplace2d_64", m=30)
+    A, B = gpu_ops(cfg)
+    prm = dict(k=2, maxit=40, p=10, s=336, tol=0.0, seed=8)
+    f = skr.solve(A, B, to_dev(cfg["C1"]), to_dev(cfg["C2"]), **prm)
+    a = skr.adjoint_solve(A, B, to_dev(cfg["C1"]), to_dev(cfg["C2"]), **prm)
+    Xf = (f.X1 @ f.X2.T).cpu().numpy()
+    Xa = (a.X1 @ a.X2.T).cpu().numpy()
+    assert np.linalg.norm(Xf - Xa) <= 1e-12 * np.linalg.norm(Xf)

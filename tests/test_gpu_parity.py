@@ -1,0 +1,167 @@
+"""GPU (gfx950) parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Both sides run on the same seeded inputs with the same embedding seed.  Parity is judged
+on what is unique: the product X1 X2^T (the factors are unique only up to an invertible
+ell x ell transformation) and the residual estimates.  Fixed-d runs (tol = 0) keep the
+stopping step identical on both sides.  Bars: relative product distance <= 1e-6 (FP64
+bulk) and <= 1e-4 (mixed FP32/FP64); residual estimates within 1e-6 / 1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_ops, gpu_solve, history_ratio, oracle_solve, product_distance, to_dev
+from oracle.closed_form import LaplaceSylvester
+from oracle.lowrank import rel_distance
+from oracle.lowrank import true_residual as oracle_true_residual
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-6, 1e-6), "mixed": (1e-4, 1e-3)}
+
+# family, grid m (n = m^2 or m^3, never a multiple of the 256-row tile), r, solver params
+FIXED_D_CASES = [
+    ("laplace2d_64", 45, 1, dict(k=2, maxit=40, p=10, s=336, seed=1001)),
+    ("convdiff2d_1000", 37, 4, dict(k=3, maxit=24, p=8, s=800, seed=1002)),
+    ("aniso3d_100", 11, 8, dict(k=2, maxit=10, p=5, s=880, seed=1003)),
+    ("reaction2d_500", 33, 2, dict(k=2, maxit=30, p=10, s=496, seed=1004)),
+    ("lognormal2d_2000", 30, 10, dict(k=2, maxit=8, p=4, s=720, seed=1005)),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-m{c[1]}-r{c[2]}"
+
+
+@pytest.mark.parametrize("case", FIXED_D_CASES, ids=_ids)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fixed_d_parity(case, precision):
+    name, m, r, prm = case
+    cfg = make_config(name, m=m, r=r)
+    print(f"case {name} m={m} r={r} {precision}", flush=True)
+    g, _ = gpu_solve(cfg, precision=precision, tol=0.0, **prm)
+    o = oracle_solve(cfg, tol=0.0, **prm)
+    assert g.iters == o.d == prm["maxit"]
+    dist = product_distance(g, o)
+    hr = history_ratio(g, o)
+    tol_x, tol_h = TOL[precision]
+    assert dist <= tol_x, dist
+    assert hr <= tol_h, hr
+
+
+def test_converged_run_matches_oracle_and_closed_form():
+    cfg = make_config("laplace2d_64", m=40)
+    prm = dict(k=2, maxit=200, p=10, s=400, tol=1e-8, seed=1001)
+    g, _ = gpu_solve(cfg, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert g.status == o.status == "converged"
+    assert g.iters == o.d
+    assert product_distance(g, o) <= 1e-6
+    cf = LaplaceSylvester(40, cfg["C1"], cfg["C2"])
+    assert cf.rel_error(g.X1.cpu().numpy(), g.X2.cpu().numpy()) <= 1e-6
+
+
+def test_laplace_64_full_size_closed_form():
+    """The 64 x 64 Laplacian pair (n = 4096, r = 1, k = 2): needs more than 100 steps for
+    1e-8, so maxit is raised; the solution is checked against the sine-transform solution."""
+    cfg = make_config("laplace2d_64")
+    g, (A, B) = gpu_solve(cfg, k=2, maxit=300, p=20, s=600, tol=1e-8, seed=cfg["sketch_seed"])
+    assert g.status == "converged"
+    cf = LaplaceSylvester(64, cfg["C1"], cfg["C2"])
+    assert cf.rel_error(g.X1.cpu().numpy(), g.X2.cpu().numpy()) <= 1e-6
+    import paper_2311_16019_amd as skr
+    tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    assert tr <= 5e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_pass_recovery_matches_stored(precision):
+    cfg = make_config("convdiff2d_1000", m=29, r=2)
+    prm = dict(k=3, maxit=30, p=10, s=496, tol=0.0, seed=7, precision=precision)
+    a, _ = gpu_solve(cfg, recover="stored", **prm)
+    b, _ = gpu_solve(cfg, recover="two_pass", **prm)
+    d = rel_distance(b.X1.cpu().numpy(), b.X2.cpu().numpy(), a.X1.cpu().numpy(), a.X2.cpu().numpy())
+    assert d <= (1e-8 if precision == "fp64" else 1e-4), d
+
+
+def test_true_residual_matches_oracle_evaluation():
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=31, r=3)
+    g, (A, B) = gpu_solve(cfg, k=3, maxit=20, p=10, s=480, tol=0.0, seed=3)
+    tr_gpu = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    tr_orc = oracle_true_residual(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], g.X1.cpu().numpy(), g.X2.cpu().numpy())
+    assert abs(tr_gpu / tr_orc - 1) <= 1e-8
+
+
+@pytest.mark.parametrize("m", [4, 5, 16])
+def test_tiny_and_single_tile_sizes(m):
+    """n = 16, 25, 256: fewer rows than one tile, and exactly one tile."""
+    cfg = make_config("convdiff2d_1000", m=m, r=2)
+    maxit = min(6, cfg["n"] // 2 - 1)
+    prm = dict(k=2, maxit=maxit, p=maxit, s=8 * maxit + 8, tol=0.0, seed=11)
+    g, _ = gpu_solve(cfg, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert product_distance(g, o) <= 1e-6
+
+
+def test_largest_block_size_r16():
+    cfg = make_config("convdiff2d_1000", m=26, r=16)
+    prm = dict(k=2, maxit=5, p=5, s=1024, tol=0.0, seed=13)
+    g, _ = gpu_solve(cfg, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert product_distance(g, o) <= 1e-6
+
+
+@pytest.mark.parametrize("zeta", [1, 4])
+def test_other_sparsity_of_the_embedding(zeta):
+    cfg = make_config("convdiff2d_1000", m=20, r=2)
+    prm = dict(k=2, maxit=10, p=5, s=160, tol=0.0, seed=17, zeta=zeta)
+    g, _ = gpu_solve(cfg, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert product_distance(g, o) <= 1e-6
+
+
+def test_breakdown_on_invariant_krylov_space():
+    import paper_2311_16019_amd as skr
+    import scipy.sparse as sp
+    from workloads.stencil import CSR
+    n = 300
+    A = CSR.from_scipy(sp.diags(np.tile([1.0, 2.0, 4.0], n // 3)))
+    rng = np.random.Generator(np.random.PCG64(1))
+    B = CSR.from_scipy(sp.diags(np.linspace(1, 3, n)) + sp.random(n, n, density=0.01, random_state=3))
+    cfg = dict(A=A, B=B, sigma=None, C1=rng.standard_normal((n, 1)), C2=rng.standard_normal((n, 1)))
+    prm = dict(k=2, maxit=10, p=5, s=96, tol=0.0, seed=5)
+    g, _ = gpu_solve(cfg, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert g.status == o.status == "breakdown"
+    assert g.iters == o.d == 3
+    assert product_distance(g, o) <= 1e-6
+
+
+def test_invalid_parameters_are_rejected():
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=10, r=2)
+    A, B = gpu_ops(cfg)
+    C1, C2 = to_dev(cfg["C1"]), to_dev(cfg["C2"])
+    for bad in (dict(s=100, zeta=8), dict(k=0), dict(maxit=0), dict(s=8, maxit=10)):
+        with pytest.raises(skr.SkrError) as ei:
+            skr.solve(A, B, C1, C2, **bad)
+        assert ei.value.code == -1
+    Z = to_dev(np.zeros((cfg["n"], 2)))
+    with pytest.raises(skr.SkrError):
+        skr.solve(A, B, Z, C2, maxit=5, p=5, s=48)
+
+
+def test_full_size_convdiff_fixed_d():
+    """The 1000 x 1000 convection-diffusion pair (n = 1e6, r = 4, k = 3, s = 8000) at the
+    launch configuration the benchmark uses, compared with the oracle at d = 20."""
+    cfg = make_config("convdiff2d_1000")
+    prm = dict(k=3, maxit=20, p=20, s=cfg["s"], tol=0.0, seed=cfg["sketch_seed"])
+    for precision in ("fp64", "mixed"):
+        print(f"full-size convdiff {precision}", flush=True)
+        g, _ = gpu_solve(cfg, precision=precision, **prm)
+        if precision == "fp64":
+            o = oracle_solve(cfg, **prm)
+        dist = product_distance(g, o)
+        assert dist <= TOL[precision][0], (precision, dist)
+        assert history_ratio(g, o) <= TOL[precision][1]
