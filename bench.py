@@ -1,0 +1,203 @@
+"""Benchmark: Krylov block steps/s of the s-PKSM hot path at n = 1e6 on one MI355X.
+
+One benchmark step = a forward solve of A X + X B = C1 C2^T and the adjoint solve
+A^T L + L B^T = P1 P2^T with the same method, then the gradients of tr(P1^T X P2), on the
+1000 x 1000 upwind convection-diffusion pair (n = 1e6, r = 4, k = 3, s = 8000,
+nu = 1e-2, w_A = (1, 0.5), w_B = (-0.3, 1)).  Each solve runs a fixed window of d block
+steps (tandem SpMM, truncated block Gram-Schmidt, sketch, sketched QR update), one
+projected FP64 Sylvester solve with the residual estimate, the low-rank factorisation and
+the stored-basis recovery.  `value` = tandem block steps (forward + adjoint) per second
+of wall time over the whole step, inputs resident in HBM.
+
+Also reported: the same step in plain FP64, the per-kernel roofline of the dominant
+kernel family (HIP events inside the timed region), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "convdiff2d_1000"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--window", type=int, default=200, help="block steps per solve")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(family, cfg, w, d_avg):
+    """Bytes one launch of a kernel family must move (both Krylov spaces), by its definition.
+
+    w = bulk element size.  Blocks are n x r; CSR = nnz (w + 4) + 4 (n + 1).
+    """
+    n, r, s = cfg["n"], cfg["r"], cfg["s"]
+    tot = 0
+    for M, diag in ((cfg["A"], cfg["sigma"] is not None), (cfg["B"], False)):
+        nnz = M.nnz
+        blk = n * r * w
+        if family == "spmm_dot":      # CSR once, U_d read, U~ written, first window block read
+            tot += nnz * (w + 4) + 4 * (n + 1) + 3 * blk + (8 * n if diag else 0)
+        elif family == "axpy_reduce":  # U~ read+written, U_i read, U_{i+1} read (averaged)
+            tot += 3 * blk + blk * (2.0 / 3.0)
+        elif family == "gram2":
+            tot += blk
+        elif family == "normalize":
+            tot += 2 * blk
+        elif family == "sketch":       # U_{d+1} read once, table read, s x r FP64 written
+            tot += blk + 2 * n * 8 + 8 * s * r
+        elif family == "whiten":       # two Gram-Schmidt passes over Q (s x d r FP64)
+            tot += 2 * 8 * s * r * d_avg
+    return tot
+
+
+def cpu_baseline(cfg, steps):
+    """The FP64 oracle's tandem block steps/s on the same matrices (bounded sample)."""
+    from oracle import sketch as osk
+    from oracle.spksm import Space, as_operator
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    A = as_operator(cfg["A"])
+    BT = as_operator(cfg["B"]).T.tocsr()
+    sig = cfg["sigma"]
+    su, sv = osk.space_seeds(cfg["sketch_seed"])
+    SU = osk.sparse_sign(cfg["n"], cfg["s"], 8, su)
+    SV = osk.sparse_sign(cfg["n"], cfg["s"], 8, sv)
+    opu = (lambda X: A @ X) if sig is None else (lambda X: A @ X + sig[:, None] * X)
+    U = Space(opu, SU, cfg["k"], cfg["r"], steps + 1, False)
+    V = Space(lambda X: BT @ X, SV, cfg["k"], cfg["r"], steps + 1, False)
+    U.init(cfg["C1"])
+    V.init(cfg["C2"])
+    t0 = time.perf_counter()
+    for d in range(1, steps + 1):
+        U.step(d)
+        V.step(d)
+    el = time.perf_counter() - t0
+    return dict(value=steps / el, unit="tandem block steps/s", cores=int(threads), kind="oracle",
+                sample=f"{steps} tandem block steps (d = 1..{steps}) of the FP64 oracle on the n = 1e6 "
+                       f"convection-diffusion pair (SpMM, truncated MGS, QR, sketch, sketched QR update); "
+                       f"{el:.1f} s; SciPy sparse products single-threaded, BLAS threads = {threads}")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2311_16019_amd as skr
+    from workloads import make_config
+
+    cfg = make_config(WORKLOAD)  # s = 8000 (4 * 500 * r), k = 3, r = 4, tol 1e-6
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    A = skr.Operator.from_csr(cfg["A"].indptr, cfg["A"].indices, cfg["A"].data, diag=cfg["sigma"])
+    B = skr.Operator.from_csr(cfg["B"].indptr, cfg["B"].indices, cfg["B"].data)
+    C1, C2, P1, P2 = dev(cfg["C1"]), dev(cfg["C2"]), dev(cfg["P1"]), dev(cfg["P2"])
+    win = args.window
+
+    def params(precision, profile=False):
+        return dict(k=cfg["k"], maxit=win, p=win, s=cfg["s"], tol=cfg["tol"], seed=cfg["sketch_seed"],
+                    precision=precision, recover="stored", profile=profile)
+
+    def one_step(precision, profile=False):
+        prm = params(precision, profile)
+        f = skr.solve(A, B, C1, C2, **prm)
+        a = skr.adjoint_solve(A, B, P1, P2, **prm)
+        g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
+        return f, a, g
+
+    # warmup with every kernel family timed: find the dominant family
+    fam_total = {}
+    for _ in range(max(1, args.warmup)):
+        f, a, _ = one_step(args.precision, profile=True)
+        for res in (f, a):
+            for k, (nl, ms) in res.kernels.items():
+                fam_total[k] = fam_total.get(k, 0.0) + ms
+    dominant = max(fam_total, key=fam_total.get)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fam = {}
+    steps_done = 0
+    split = dict(steps=0.0, proj=0.0, recover=0.0)
+    last = None
+    for _ in range(args.steps):
+        f, a, g = one_step(args.precision, profile=True)
+        for res in (f, a):
+            steps_done += res.iters
+            split["steps"] += res.ms_steps
+            split["proj"] += res.ms_proj
+            split["recover"] += res.ms_recover
+            for k, (nl, ms) in res.kernels.items():
+                L, M = fam.get(k, (0, 0.0))
+                fam[k] = (L + nl, M + ms)
+        last = (f, a, g)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = 1000.0 * el / args.steps
+    value = steps_done / el
+
+    f, a, g = last
+    true_res = skr.true_residual(A, B, f.X1, f.X2, C1, C2)
+    w = 4 if args.precision == "mixed" else 8
+    nl, ms = fam[dominant]
+    d_avg = (win + 1) / 2.0
+    per_launch = algorithmic_bytes(dominant, cfg, w, d_avg)
+    achieved = per_launch / (ms / nl * 1e-3) / 1e9
+    roofline = dict(kernel=dominant, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
+    families = {k: dict(launches=v[0], avg_us=round(1000.0 * v[1] / v[0], 2),
+                        gbs=round(algorithmic_bytes(k, cfg, w, d_avg) / (v[1] / v[0] * 1e-3) / 1e9, 1))
+                for k, v in fam.items()}
+
+    out = dict(metric="Krylov tandem block steps/s at n=1M (forward + adjoint s-PKSM)", value=round(value, 2),
+               unit="block steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32+f64" if args.precision == "mixed"
+               else "f64", data="synthetic",
+               config=dict(workload="upwind convection-diffusion 1000x1000 pair (n=1e6), r=4, k=3, s=8000, "
+                                    f"{win} block steps per solve, forward + adjoint, stored-basis recovery",
+                           n=cfg["n"], r=cfg["r"], k=cfg["k"], s=cfg["s"], window=win, precision=args.precision),
+               roofline=roofline, kernel_families=families,
+               time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
+                                  projected_solves=round(split["proj"] / args.steps, 2),
+                                  recovery=round(split["recover"] / args.steps, 2)),
+               forward=dict(iters=f.iters, rho_rel=f.rho_rel, true_residual=true_res, ell=f.ell, status=f.status,
+                            projected=f.proj),
+               adjoint=dict(iters=a.iters, rho_rel=a.rho_rel, ell=a.ell, projected=a.proj))
+    if not args.no_fp64_compare and args.precision == "mixed":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f64, a64, _ = one_step("fp64")
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t1
+        out["fp64_step"] = dict(ms=round(1000.0 * el64, 2), block_steps_per_s=round((f64.iters + a64.iters) / el64, 2),
+                                speedup_mixed_over_fp64=round(1000.0 * el64 / ms_step, 3),
+                                rho_rel=f64.rho_rel)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

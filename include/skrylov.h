@@ -68,6 +68,9 @@ enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
  *   sketch    SKR_SKETCH_SPARSE_SIGN
  *   recover   SKR_RECOVER_STORED (keep every basis block in HBM) or
  *             SKR_RECOVER_TWO_PASS (keep k+1 blocks, regenerate them for the factors)
+ *   profile   nonzero: record HIP events around every launch of each kernel family of
+ *             the block step (adds a few microseconds per launch); see
+ *             skr_result_kernel_stats
  *   trunc_tol relative Frobenius cutoff of the low-rank factorisation of the projected
  *             solution Y (0 keeps everything)
  */
@@ -82,7 +85,7 @@ typedef struct {
   int32_t precision;
   int32_t sketch;
   int32_t recover;
-  int32_t reserved0;
+  int32_t profile;
   double trunc_tol;
 } skr_params;
 
@@ -148,6 +151,19 @@ SKR_API int skr_result_copy_factors(skr_result res, double* X1, double* X2, void
 /* Device-time breakdown of the solve in milliseconds (HIP events): block steps,
  * projected solves (incl. residual estimates), recovery.  Any pointer may be NULL. */
 SKR_API int skr_result_timing(skr_result res, double* ms_steps, double* ms_proj, double* ms_recover);
+
+/* Per-kernel-family device time of a solve run with params.profile != 0: family `idx`
+ * (0 .. count-1) has a static name, a number of launches and their summed duration in
+ * milliseconds (HIP events on the solve's stream).  *count receives the number of
+ * families; idx out of range returns SKR_EINVAL. */
+SKR_API int skr_result_kernel_stats(skr_result res, int32_t idx, int32_t* count, const char** name,
+                                    int64_t* launches, double* ms);
+
+/* Diagnostics of the last projected solve (eqn:reduced_sk) of a result: Newton steps of the
+ * sign iteration, eigenvalues of the two projected matrices in the left half plane (handled
+ * by deflation), and the relative residual of the projected Sylvester equation. */
+SKR_API int skr_result_proj_stats(skr_result res, int32_t* newton_iters, int32_t* neg_a, int32_t* neg_b,
+                                  double* proj_resid);
 
 SKR_API int skr_result_destroy(skr_result res);
 

@@ -118,10 +118,12 @@ class Result:
     ms_steps: float = 0.0
     ms_proj: float = 0.0
     ms_recover: float = 0.0
+    kernels: dict = field(default_factory=dict)  # family -> (launches, total ms), profile=True only
+    proj: dict = field(default_factory=dict)     # last projected solve: newton_iters, neg_a, neg_b, resid
 
 
 def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64", recover="stored",
-            trunc_tol=1e-12):
+            trunc_tol=1e-12, profile=False):
     prm = _lib.Params()
     _lib.check(_lib.load().skr_params_default(ctypes.byref(prm)))
     prm.k, prm.maxit, prm.p, prm.s, prm.tol = int(k), int(maxit), int(p), int(s), float(tol)
@@ -129,6 +131,7 @@ def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64
     prm.precision = {"fp64": _lib.SKR_FP64, "mixed": _lib.SKR_MIXED}[precision]
     prm.recover = {"stored": _lib.SKR_RECOVER_STORED, "two_pass": _lib.SKR_RECOVER_TWO_PASS}[recover]
     prm.sketch = _lib.SKR_SKETCH_SPARSE_SIGN
+    prm.profile = 1 if profile else 0
     return prm
 
 
@@ -148,10 +151,21 @@ def _collect(h, n1, n2, stream):
     _lib.check(lib.skr_result_history(h, d, rr, ln.value, ctypes.byref(ln)))
     t = [ctypes.c_double() for _ in range(3)]
     _lib.check(lib.skr_result_timing(h, *(ctypes.byref(x) for x in t)))
+    kernels = {}
+    cnt = ctypes.c_int32()
+    _lib.check(lib.skr_result_kernel_stats(h, 0, ctypes.byref(cnt), None, None, None))
+    for i in range(cnt.value):
+        nm, nl, ms = ctypes.c_char_p(), ctypes.c_int64(), ctypes.c_double()
+        _lib.check(lib.skr_result_kernel_stats(h, i, None, ctypes.byref(nm), ctypes.byref(nl), ctypes.byref(ms)))
+        if nl.value:
+            kernels[nm.value.decode()] = (nl.value, ms.value)
+    ni, na, nb, pr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _lib.check(lib.skr_result_proj_stats(h, ctypes.byref(ni), ctypes.byref(na), ctypes.byref(nb), ctypes.byref(pr)))
     return Result(X1=X1, X2=X2, iters=iters.value, ell=ell.value, rho_rel=rho.value,
                   status=_lib.STATUS_NAMES.get(st.value, str(st.value)),
                   history=[(d[i], rr[i]) for i in range(ln.value)],
-                  ms_steps=t[0].value, ms_proj=t[1].value, ms_recover=t[2].value)
+                  ms_steps=t[0].value, ms_proj=t[1].value, ms_recover=t[2].value, kernels=kernels,
+                  proj=dict(newton_iters=ni.value, neg_a=na.value, neg_b=nb.value, resid=pr.value))
 
 
 def _run(entry, A, B, C1, C2, stream, **params):

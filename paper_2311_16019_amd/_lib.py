@@ -28,7 +28,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("sketch", ctypes.c_int32),
         ("recover", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("trunc_tol", ctypes.c_double),
     ]
 
@@ -56,6 +56,8 @@ SIGNATURES = {
     "skr_result_history": (_i32, [_vp, _pi32, _pf64, _i32, _pi32]),
     "skr_result_copy_factors": (_i32, [_vp, _vp, _vp, _vp]),
     "skr_result_timing": (_i32, [_vp, _pf64, _pf64, _pf64]),
+    "skr_result_kernel_stats": (_i32, [_vp, _i32, _pi32, ctypes.POINTER(ctypes.c_char_p), _pi64, _pf64]),
+    "skr_result_proj_stats": (_i32, [_vp, _pi32, _pi32, _pi32, _pf64]),
     "skr_result_destroy": (_i32, [_vp]),
     "skr_true_residual": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),
     "skr_pairing_grads": (_i32, [_i64, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,

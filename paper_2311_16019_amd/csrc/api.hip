@@ -293,6 +293,30 @@ int skr_result_timing(skr_result res, double* ms_steps, double* ms_proj, double*
   });
 }
 
+int skr_result_kernel_stats(skr_result res, int32_t idx, int32_t* count, const char** name, int64_t* launches,
+                            double* ms) {
+  return guarded([&] {
+    SKR_REQUIRE(res, "null result");
+    if (count) *count = KF_COUNT;
+    SKR_REQUIRE(idx >= 0 && idx < KF_COUNT, "kernel family index out of range");
+    if (name) *name = kernel_family_name(idx);
+    if (launches) *launches = res->fam_launches[idx];
+    if (ms) *ms = res->fam_ms[idx];
+    return SKR_OK;
+  });
+}
+
+int skr_result_proj_stats(skr_result res, int32_t* newton_iters, int32_t* neg_a, int32_t* neg_b, double* proj_resid) {
+  return guarded([&] {
+    SKR_REQUIRE(res, "null result");
+    if (newton_iters) *newton_iters = res->last_stats.newton_iters;
+    if (neg_a) *neg_a = res->last_stats.neg_eigs_a;
+    if (neg_b) *neg_b = res->last_stats.neg_eigs_b;
+    if (proj_resid) *proj_resid = res->last_stats.proj_resid;
+    return SKR_OK;
+  });
+}
+
 int skr_result_destroy(skr_result res) {
   delete res;
   return SKR_OK;

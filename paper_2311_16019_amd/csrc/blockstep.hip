@@ -12,7 +12,6 @@
 namespace skr {
 namespace {
 
-constexpr int PSTRIDE = RMAX * RMAX + 8;  // doubles per workgroup partial
 
 // Logical workgroup id such that each XCD (workgroups are dealt round-robin over the 8
 // XCDs by hardware id) owns a contiguous range of logical ids, hence contiguous rows.
@@ -119,7 +118,8 @@ __device__ void post_process(const SpaceStep<T>& sp, int r) {
     }
   } else {  // POST_GRAM2
     if (*sp.broken == sp.step) return;
-    double R2[RMAX * RMAX], R2i[RMAX * RMAX];
+    double* R2 = sm + SmallLayout::SIZE;  // scratch past the state (LDS in reduce_post_kernel)
+    double* R2i = R2 + RMAX * RMAX;
     if (!chol_upper(out, R2, r)) {
       mark_broken(sp, sm, r);
     } else {
@@ -140,37 +140,43 @@ __device__ void post_process(const SpaceStep<T>& sp, int r) {
   }
 }
 
-// Workgroup-level epilogue: reduce per-thread r x r (+1 extra) accumulators into a
-// partial, then let the last-arriving workgroup reduce all partials and post-process.
-// `acc` holds, for thread-private accumulation (R <= 6), the full r x r products; for the
-// LDS path the caller passes the already reduced pair sums through `lds_pair`.
-template <typename T, int R>
-__device__ void finish_reduction(const SpaceStep<T>& sp, int local, const double* wg_vals, int nvals) {
-  // wg_vals: nvals values (already reduced over the workgroup, visible to all threads)
-  double* part = sp.part + (size_t)local * PSTRIDE;
-  for (int i = threadIdx.x; i < nvals; i += blockDim.x) part[i] = wg_vals[i];
-  __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(sp.counter, 1u);
-    am_last = (t == (unsigned)(sp.nwg - 1));
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
+// Workgroup epilogue: write this workgroup's reduced values as its partial, value-major
+// (part[i * nwg + local]) so that the reduction reads each value's partials contiguously.
+// The partials are summed in a fixed order by reduce_post_kernel, launched next on the
+// same stream (the kernel boundary makes them visible; no device-scope fence is needed).
+template <typename T>
+__device__ inline void write_partial(const SpaceStep<T>& sp, int local, const double* wg_vals, int nvals) {
+  for (int i = threadIdx.x; i < nvals; i += blockDim.x) sp.part[(size_t)i * sp.nwg + local] = wg_vals[i];
+}
+
+// One workgroup per space: each wavefront sums the partials of some values (lane-strided,
+// coalesced, then a fixed shuffle tree), then one thread post-processes.
+template <typename T>
+__global__ void __launch_bounds__(256) reduce_post_kernel(SpaceStep<T> s0, SpaceStep<T> s1, int r, int nvals) {
+  const SpaceStep<T>& sp = blockIdx.x ? s1 : s0;
   double* out = sp.small + SmallLayout::OUT;
-  for (int i = threadIdx.x; i < nvals; i += blockDim.x) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  for (int i = wv; i < nvals; i += 4) {
+    const double* p = sp.part + (size_t)i * sp.nwg;
     double s = 0.0;
-    for (int w = 0; w < sp.nwg; ++w) s += sp.part[(size_t)w * PSTRIDE + i];
-    out[i] = s;
+    for (int w = lane; w < sp.nwg; w += 64) s += p[w];
+    s = wave_sum(s);
+    if (lane == 0) out[i] = s;
   }
   __syncthreads();
+  // post-process on an LDS copy of the small state (the single thread's dependent
+  // accesses then hit LDS, not global memory), then write it back
+  __shared__ double sm[SmallLayout::SIZE + 2 * RMAX * RMAX];
+  for (int i = threadIdx.x; i < SmallLayout::SIZE; i += blockDim.x) sm[i] = sp.small[i];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (nvals > R * R) sp.small[SmallLayout::NRMOP] = out[R * R];
-    post_process(sp, R);
-    *sp.counter = 0u;
+    if (nvals > r * r) sm[SmallLayout::NRMOP] = sm[SmallLayout::OUT + r * r];
+    SpaceStep<T> loc = sp;
+    loc.small = sm;
+    post_process(loc, r);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SmallLayout::SIZE; i += blockDim.x) sp.small[i] = sm[i];
 }
 
 // Accumulate r x r products  sum_rows P[row][a] * Q[row][b]  of one tile of WG rows.
@@ -340,7 +346,7 @@ __global__ void __launch_bounds__(WG) spmm_dot_kernel(SpaceStep<T> s0, SpaceStep
     pair_accumulate<R>(acc, w, y, lds_p, lds_q);
   }
   pair_reduce<R>(acc, sq, vals, scratch);
-  finish_reduction<T, R>(sp, wi.local, vals, R * R + 1);
+  write_partial(sp, wi.local, vals, R * R + 1);
 }
 
 // Y -= W * coef;  then partials of Wn^T Y (dot) or Y^T Y (Gram).
@@ -388,7 +394,7 @@ __global__ void __launch_bounds__(WG) axpy_reduce_kernel(SpaceStep<T> s0, SpaceS
     pair_accumulate<R>(acc, p, y, lds_p, lds_q);
   }
   pair_reduce<R>(acc, 0.0, vals, scratch);
-  finish_reduction<T, R>(sp, wi.local, vals, R * R);
+  write_partial(sp, wi.local, vals, R * R);
 }
 
 // Gram matrix of Y R1^{-1} (second Cholesky QR pass); Y is not modified.
@@ -423,7 +429,7 @@ __global__ void __launch_bounds__(WG) gram2_kernel(SpaceStep<T> s0, SpaceStep<T>
     pair_accumulate<R>(acc, z, z, lds_p, lds_q);
   }
   pair_reduce<R>(acc, 0.0, vals, scratch);
-  finish_reduction<T, R>(sp, wi.local, vals, R * R);
+  write_partial(sp, wi.local, vals, R * R);
 }
 
 // Unew = Y R^{-1}.
@@ -549,19 +555,28 @@ int sketch_chunks(int n) { return std::max(1, std::min(16, ceil_div(n, 4 * SK_WG
   }
 
 template <typename T>
+void launch_reduce_post(int r, int nvals, const SpaceStep<T>& s0, const SpaceStep<T>& s1, hipStream_t st) {
+  hipLaunchKernelGGL((reduce_post_kernel<T>), dim3(2), dim3(256), 0, st, s0, s1, r, nvals);
+  check_launch("reduce_post");
+}
+
+template <typename T>
 void launch_spmm_dot(int r, const SpaceStep<T>& s0, const SpaceStep<T>& s1, hipStream_t st) {
   SKR_DISPATCH_R(r, hipLaunchKernelGGL((spmm_dot_kernel<T, RR_>), dim3(grid_of(s0, s1)), dim3(WG), 0, st, s0, s1));
   check_launch("spmm_dot");
+  launch_reduce_post(r, r * r + 1, s0, s1, st);
 }
 template <typename T>
 void launch_axpy_reduce(int r, const SpaceStep<T>& s0, const SpaceStep<T>& s1, hipStream_t st) {
   SKR_DISPATCH_R(r, hipLaunchKernelGGL((axpy_reduce_kernel<T, RR_>), dim3(grid_of(s0, s1)), dim3(WG), 0, st, s0, s1));
   check_launch("axpy_reduce");
+  launch_reduce_post(r, r * r, s0, s1, st);
 }
 template <typename T>
 void launch_gram2(int r, const SpaceStep<T>& s0, const SpaceStep<T>& s1, hipStream_t st) {
   SKR_DISPATCH_R(r, hipLaunchKernelGGL((gram2_kernel<T, RR_>), dim3(grid_of(s0, s1)), dim3(WG), 0, st, s0, s1));
   check_launch("gram2");
+  launch_reduce_post(r, r * r, s0, s1, st);
 }
 template <typename T>
 void launch_normalize(int r, const SpaceStep<T>& s0, const SpaceStep<T>& s1, hipStream_t st) {

@@ -36,7 +36,6 @@ struct SpaceStep {
   T* Unew;              // destination of the normalised block (normalize only)
   double* small;        // SmallLayout state
   double* part;         // per-workgroup partials
-  unsigned* counter;    // arrival counter for the last-workgroup reduction (must start at 0)
   int* broken;          // first step at which this space broke down (INT_MAX if none)
   double* Hblk;         // destination of h (column-major block in H), or null
   int ldh;

@@ -42,46 +42,47 @@ struct LoadBasis {  // (i, q) -> U_{q / r}[i][q % r] for consecutive row-major n
     return static_cast<double>(U[((size_t)j * n + i) * r + c]);
   }
 };
-struct StoreCM {  // column-major C
-  double* C; int ldc; double alpha, beta;
-  __device__ void operator()(int i, int j, double v) const {
-    double* p = C + i + (size_t)j * ldc;
+struct StoreCM {  // column-major C; K-slice z writes to C + z * zstride
+  double* C; int ldc; double alpha, beta; size_t zstride = 0;
+  __device__ void operator()(int i, int j, double v, int z) const {
+    double* p = C + (size_t)z * zstride + i + (size_t)j * ldc;
     *p = (beta == 0.0) ? alpha * v : alpha * v + beta * *p;
   }
 };
 struct StoreRM {  // row-major C (element (i, j) at i*ldc + j)
-  double* C; int ldc; double alpha, beta;
-  __device__ void operator()(int i, int j, double v) const {
-    double* p = C + (size_t)i * ldc + j;
+  double* C; int ldc; double alpha, beta; size_t zstride = 0;
+  __device__ void operator()(int i, int j, double v, int z) const {
+    double* p = C + (size_t)z * zstride + (size_t)i * ldc + j;
     *p = (beta == 0.0) ? alpha * v : alpha * v + beta * *p;
   }
 };
 
 template <class LA, class LB, class ST>
-__global__ void __launch_bounds__(GT) gemm_kernel(int m, int n, int k, LA la, LB lb, ST st) {
+__global__ void __launch_bounds__(GT) gemm_kernel(int m, int n, int k, LA la, LB lb, ST st, int kchunk) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int kb = blockIdx.z * kchunk, ke = min(k, kb + kchunk);
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int k0 = 0; k0 < k; k0 += BK) {
+  for (int k0 = kb; k0 < ke; k0 += BK) {
 #pragma unroll
     for (int e = tid; e < BM * BK; e += GT) {
       int ii, kk;
       if constexpr (LA::I_FAST) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
       const int gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < m && gk < k) ? la(gi, gk) : 0.0;
+      As[kk][ii] = (gi < m && gk < ke) ? la(gi, gk) : 0.0;
     }
 #pragma unroll
     for (int e = tid; e < BN * BK; e += GT) {
       int jj, kk;
       if constexpr (LB::K_FAST) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
       const int gj = j0 + jj, gk = k0 + kk;
-      Bs[kk][jj] = (gj < n && gk < k) ? lb(gk, gj) : 0.0;
+      Bs[kk][jj] = (gj < n && gk < ke) ? lb(gk, gj) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -103,32 +104,87 @@ __global__ void __launch_bounds__(GT) gemm_kernel(int m, int n, int k, LA la, LB
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = i0 + tx + 16 * u, j = j0 + ty + 16 * v;
-      if (i < m && j < n) st(i, j, acc[u][v]);
+      if (i < m && j < n) st(i, j, acc[u][v], blockIdx.z);
     }
+}
+
+// C = alpha * sum_z W[z] + beta * C  (column-major m x n, W slices contiguous m x n)
+__global__ void splitk_reduce_kernel(int m, int n, int nz, const double* W, double alpha, double beta, double* C,
+                                     int ldc) {
+  const size_t total = (size_t)m * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int z = 0; z < nz; ++z) t += W[(size_t)z * total + e];
+    const int i = (int)(e % m), j = (int)(e / m);
+    double* p = C + i + (size_t)j * ldc;
+    *p = (beta == 0.0) ? alpha * t : alpha * t + beta * *p;
+  }
 }
 
 template <class LA, class LB, class ST>
 void run_gemm(int m, int n, int k, LA la, LB lb, ST st, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
   dim3 grid(ceil_div(m, BM), ceil_div(n, BN));
-  hipLaunchKernelGGL((gemm_kernel<LA, LB, ST>), grid, dim3(GT), 0, s, m, n, k, la, lb, st);
+  hipLaunchKernelGGL((gemm_kernel<LA, LB, ST>), grid, dim3(GT), 0, s, m, n, k, la, lb, st, std::max(k, 1));
   check_launch("gemm");
+}
+
+// Few output tiles and a long reduction: split K over workgroups into partial products
+// and sum them in a fixed order (column-major C only).
+template <class LA, class LB>
+bool run_gemm_splitk(int m, int n, int k, LA la, LB lb, double alpha, double beta, double* C, int ldc, hipStream_t s) {
+  const int tiles = ceil_div(m, BM) * ceil_div(n, BN);
+  if (tiles >= 64 || k < 8192) return false;
+  int nz = std::min(512 / tiles + 1, ceil_div(k, 2048));
+  nz = std::max(2, std::min(nz, 256));
+  const int kchunk = ceil_div(ceil_div(k, nz), BK) * BK;
+  nz = ceil_div(k, kchunk);
+  DBuf<double> W((size_t)nz * m * n);
+  StoreCM sw{W.p, m, 1.0, 0.0, (size_t)m * n};
+  dim3 grid(ceil_div(m, BM), ceil_div(n, BN), nz);
+  hipLaunchKernelGGL((gemm_kernel<LA, LB, StoreCM>), grid, dim3(GT), 0, s, m, n, k, la, lb, sw, kchunk);
+  check_launch("gemm_splitk");
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(std::min(2048, ceil_div((int64_t)m * n, 256))), dim3(256), 0, s, m, n,
+                     nz, W.p, alpha, beta, C, ldc);
+  check_launch("splitk_reduce");
+  SKR_HIP(hipStreamSynchronize(s));  // W is released on return
+  return true;
 }
 
 // ----------------------------------------------------------------------------- LU
 constexpr int NB = 32;     // LU / TRSM block size
-constexpr int PT = 1024;   // panel threads
+constexpr int PT = 512;    // panel threads
 
-__global__ void __launch_bounds__(PT) panel_kernel(int n, double* A, int lda, int j0, int nb, int* ipiv, int* info) {
+constexpr int PANEL_LDS_DOUBLES = 16384;  // 128 KB: panels up to rows * nb <= 16384 live in LDS
+constexpr int MAXSWAP = 2 * NB;
+
+// Factor columns [j0, j0+nb) of the n x n matrix A over rows [j0, n) with partial pivoting.
+// The panel is staged in LDS when it fits (otherwise it is factored in place in global
+// memory).  Besides ipiv, the kernel writes the net row permutation of the panel's
+// interchanges as at most 2 nb (destination, source) pairs for the gather in laswp_kernel.
+__global__ void __launch_bounds__(PT) panel_kernel(int n, double* A, int lda, int j0, int nb, int* ipiv, int* info,
+                                                   int* swaps) {
+  extern __shared__ double P[];  // rows x nb, column-major with ld = rows (when staged)
   __shared__ double wval[PT / 64];
   __shared__ int widx[PT / 64];
   __shared__ int piv;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  for (int c = j0; c < j0 + nb; ++c) {
+  const int rows = n - j0;
+  const bool staged = (size_t)rows * nb <= PANEL_LDS_DOUBLES;
+  double* base = staged ? P : A + j0 + (size_t)j0 * lda;
+  const int ld = staged ? rows : lda;
+  if (staged) {
+    for (int e = tid; e < rows * nb; e += PT) {
+      const int i = e % rows, c = e / rows;
+      P[e] = A[(j0 + i) + (size_t)(j0 + c) * lda];
+    }
+    __syncthreads();
+  }
+  for (int c = 0; c < nb; ++c) {  // local column c = global column j0 + c
     double best = -1.0;
-    int bi = n;
-    for (int i = c + tid; i < n; i += PT) {
-      const double v = fabs(A[i + (size_t)c * lda]);
+    int bi = rows;
+    for (int i = c + tid; i < rows; i += PT) {
+      const double v = fabs(base[i + (size_t)c * ld]);
       if (v > best) { best = v; bi = i; }
     }
 #pragma unroll
@@ -141,110 +197,220 @@ __global__ void __launch_bounds__(PT) panel_kernel(int n, double* A, int lda, in
     __syncthreads();
     if (tid == 0) {
       double b = -1.0;
-      int ib = n;
+      int ib = rows;
       for (int w = 0; w < PT / 64; ++w)
         if (wval[w] > b || (wval[w] == b && widx[w] < ib)) { b = wval[w]; ib = widx[w]; }
-      if (ib >= n) ib = c;
+      if (ib >= rows) ib = c;
       piv = ib;
-      ipiv[c] = ib;
-      if (!(b > 0.0) && *info == 0) *info = c + 1;
+      ipiv[j0 + c] = j0 + ib;
+      if (!(b > 0.0) && *info == 0) *info = j0 + c + 1;
     }
     __syncthreads();
     const int p = piv;
     if (p != c)
-      for (int cc = j0 + tid; cc < j0 + nb; cc += PT) {
-        const double t = A[c + (size_t)cc * lda];
-        A[c + (size_t)cc * lda] = A[p + (size_t)cc * lda];
-        A[p + (size_t)cc * lda] = t;
+      for (int cc = tid; cc < nb; cc += PT) {
+        const double t = base[c + (size_t)cc * ld];
+        base[c + (size_t)cc * ld] = base[p + (size_t)cc * ld];
+        base[p + (size_t)cc * ld] = t;
       }
     __syncthreads();
-    const double pv = A[c + (size_t)c * lda];
-    if (pv != 0.0)
-      for (int i = c + 1 + tid; i < n; i += PT) A[i + (size_t)c * lda] /= pv;
+    const double pv = base[c + (size_t)c * ld];
+    const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+    __shared__ double prow[NB];
+    if (tid < nb) prow[tid] = base[c + (size_t)tid * ld];
     __syncthreads();
-    const int rows = n - c - 1, cols = j0 + nb - c - 1;
-    if (rows > 0 && cols > 0)
-      for (int e = tid; e < rows * cols; e += PT) {
-        const int i = c + 1 + e % rows, cc = c + 1 + e / rows;
-        A[i + (size_t)cc * lda] -= A[i + (size_t)c * lda] * A[c + (size_t)cc * lda];
+    const int rem = rows - c - 1;
+    for (int i = c + 1 + tid; i < rows; i += PT) {
+      // the row's panel entries in registers: independent loads, then the update
+      double x[NB];
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) x[cc] = (cc > c && cc < nb) ? base[i + (size_t)cc * ld] : 0.0;
+      const double xc = base[i + (size_t)c * ld];
+      const double l = (pv != 0.0) ? xc * inv : xc;
+      base[i + (size_t)c * ld] = l;
+      if (pv != 0.0) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc)
+          if (cc > c && cc < nb) base[i + (size_t)cc * ld] = x[cc] - l * prow[cc];
       }
+    }
+    (void)rem;
     __syncthreads();
+  }
+  if (staged) {
+    for (int e = tid; e < rows * nb; e += PT) {
+      const int i = e % rows, c = e / rows;
+      A[(j0 + i) + (size_t)(j0 + c) * lda] = P[e];
+    }
+  }
+  // Net permutation of the touched rows, tracked by the first wavefront: lane t holds one
+  // touched row (row_t) and the original row now stored there (src_t); each interchange
+  // finds its two lanes with a ballot and swaps their src values with shuffles.
+  if (tid < 64) {
+    int row_t = -1, src_t = -1, used = 0;
+    for (int c = 0; c < nb; ++c) {
+      const int r1 = j0 + c, r2 = ipiv[j0 + c];
+      if (r1 == r2) continue;
+      int l1 = -1, l2 = -1;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int rr = pass ? r2 : r1;
+        const unsigned long long hit = __ballot(row_t == rr);
+        int ln = hit ? __ffsll((long long)hit) - 1 : used;
+        if (!hit) {  // first time this row is touched: claim the next lane
+          if (lane == ln) { row_t = rr; src_t = rr; }
+          ++used;
+        }
+        if (pass) l2 = ln; else l1 = ln;
+      }
+      const int v1 = __shfl(src_t, l1, 64), v2 = __shfl(src_t, l2, 64);
+      if (lane == l1) src_t = v2;
+      if (lane == l2) src_t = v1;
+    }
+    const bool moved = (row_t >= 0) && (src_t != row_t);
+    const unsigned long long mv = __ballot(moved);
+    const int pos = __popcll(mv & ((1ull << lane) - 1ull));
+    if (moved) {
+      swaps[1 + 2 * pos] = row_t;
+      swaps[2 + 2 * pos] = src_t;
+    }
+    if (lane == 0) swaps[0] = __popcll(mv);
   }
 }
 
-// Apply the panel's row interchanges to the columns outside [j0, j0+nb).
-__global__ void laswp_kernel(int n, double* A, int lda, int j0, int nb, const int* ipiv) {
+// Apply the panel's row permutation to the columns outside [j0, j0+nb) as a gather.
+__global__ void __launch_bounds__(256) laswp_kernel(int n, double* A, int lda, int j0, int nb, const int* swaps) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int ncols = n - nb;
   if (t >= ncols) return;
   const int cc = t < j0 ? t : t + nb;
-  for (int c = j0; c < j0 + nb; ++c) {
-    const int p = ipiv[c];
-    if (p != c) {
-      const double x = A[c + (size_t)cc * lda];
-      A[c + (size_t)cc * lda] = A[p + (size_t)cc * lda];
-      A[p + (size_t)cc * lda] = x;
-    }
-  }
+  const int m = swaps[0];
+  double v[MAXSWAP];
+  double* col = A + (size_t)cc * lda;
+#pragma unroll
+  for (int q = 0; q < MAXSWAP; ++q)
+    if (q < m) v[q] = col[swaps[2 + 2 * q]];
+#pragma unroll
+  for (int q = 0; q < MAXSWAP; ++q)
+    if (q < m) col[swaps[1 + 2 * q]] = v[q];
 }
 
-// B[r0:r0+nb, c0:c1) <- L^{-1} B with L the unit lower nb x nb block at (r0, r0) of L.
+// Diagonal-block triangular solves.  Each workgroup inverts the nb x nb triangular block in
+// LDS (one column of the inverse per thread), then every thread multiplies its column (or
+// row) of B by the inverse: independent fused multiply-adds instead of a dependent
+// substitution chain.
+
+// B[0:nb, :] <- L^{-1} B, L unit lower triangular; one thread per column of B.
 __global__ void trsm_lln_diag_kernel(int nb, const double* L, int ldl, double* B, int ldb, int ncols) {
-  __shared__ double Ls[NB][NB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Ls[e % nb][e / nb] = L[e % nb + (size_t)(e / nb) * ldl];
+  __shared__ double Ls[NB][NB + 1], Li[NB][NB + 1];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    Ls[i][j] = (i < nb && j < nb && i > j) ? L[i + (size_t)j * ldl] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {  // column j of L^{-1} (forward substitution on e_j), in registers
+    const int j = threadIdx.x;
+    double col[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) v -= Ls[i][l] * col[l];
+      col[i] = (i >= j) ? v : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Li[i][j] = col[i];
+  }
   __syncthreads();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncols) return;
   double x[NB];
   double* b = B + (size_t)col * ldb;
 #pragma unroll
+  for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? b[i] : 0.0;
+#pragma unroll
   for (int i = 0; i < NB; ++i) {
     if (i < nb) {
-      double s = b[i];
-      for (int l = 0; l < i; ++l) s -= Ls[i][l] * x[l];
-      x[i] = s;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l <= i; ++l) s += Li[i][l] * x[l];
       b[i] = s;
     }
   }
 }
 
-// B[r0:r0+nb, :] <- U^{-1} B with U the upper nb x nb block (non-unit).
+// B[0:nb, :] <- U^{-1} B, U upper triangular (non-unit); one thread per column of B.
 __global__ void trsm_lun_diag_kernel(int nb, const double* U, int ldu, double* B, int ldb, int ncols) {
-  __shared__ double Us[NB][NB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Us[e % nb][e / nb] = U[e % nb + (size_t)(e / nb) * ldu];
+  __shared__ double Us[NB][NB + 1], Ui[NB][NB + 1];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    Us[i][j] = (i < nb && j < nb) ? (i <= j ? U[i + (size_t)j * ldu] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {  // column j of U^{-1} (backward substitution on e_j), in registers
+    const int j = threadIdx.x;
+    double col[NB];
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < NB; ++l) v -= Us[i][l] * col[l];
+      col[i] = (i <= j) ? v / Us[i][i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Ui[i][j] = col[i];
+  }
   __syncthreads();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncols) return;
   double x[NB];
   double* b = B + (size_t)col * ldb;
 #pragma unroll
-  for (int ii = NB - 1; ii >= 0; --ii) {
-    if (ii < nb) {
-      double s = b[ii];
+  for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? b[i] : 0.0;
 #pragma unroll
-      for (int l = ii + 1; l < NB; ++l)
-        if (l < nb) s -= Us[ii][l] * x[l];
-      x[ii] = s / Us[ii][ii];
-      b[ii] = x[ii];
+  for (int i = 0; i < NB; ++i) {
+    if (i < nb) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = i; l < NB; ++l) s += Ui[i][l] * x[l];
+      b[i] = s;
     }
   }
 }
 
-// B[:, c0:c0+nb] <- B T^{-1} with T the upper nb x nb diagonal block; one thread per row.
+// B[:, 0:nb] <- B T^{-1}, T upper triangular diagonal block; one thread per row of B.
 __global__ void trsm_run_diag_kernel(int nb, const double* T, int ldt, double* B, int ldb, int nrows) {
-  __shared__ double Ts[NB][NB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Ts[e % nb][e / nb] = T[e % nb + (size_t)(e / nb) * ldt];
+  __shared__ double Ts[NB][NB + 1], Ti[NB][NB + 1];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    Ts[i][j] = (i < nb && j < nb) ? (i <= j ? T[i + (size_t)j * ldt] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const int j = threadIdx.x;
+    double col[NB];
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < NB; ++l) v -= Ts[i][l] * col[l];
+      col[i] = (i <= j) ? v / Ts[i][i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Ti[i][j] = col[i];
+  }
   __syncthreads();
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= nrows) return;
   double x[NB];
 #pragma unroll
+  for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? B[row + (size_t)c * ldb] : 0.0;
+#pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < nb) {
-      double s = B[row + (size_t)c * ldb];
-      for (int l = 0; l < c; ++l) s -= x[l] * Ts[l][c];
-      x[c] = s / Ts[c][c];
-      B[row + (size_t)c * ldb] = x[c];
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l <= c; ++l) s += x[l] * Ti[l][c];
+      B[row + (size_t)c * ldb] = s;
     }
   }
 }
@@ -263,14 +429,38 @@ __global__ void logdet_kernel(int n, const double* A, int lda, double* out) {
   }
 }
 
-__global__ void permuted_identity_kernel(int n, const int* ipiv, double* X, int ldx) {
+// perm[i] = row of the identity that ends up in row i after the interchanges.  The
+// sequential interchanges run on one thread over a copy in LDS (n <= PERM_LDS).
+constexpr int PERM_LDS = 32768;
+__global__ void perm_kernel(int n, const int* ipiv, int* perm) {
+  __shared__ int pl[PERM_LDS];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) pl[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < n; ++c) {
+      const int p = ipiv[c];
+      if (p != c) { const int t = pl[c]; pl[c] = pl[p]; pl[p] = t; }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = pl[i];
+}
+
+// X = P I:  X(i, j) = [perm[i] == j]
+__global__ void permuted_identity_kernel(int n, const int* perm, double* X, int ldx) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    X[i + (size_t)j * ldx] = (perm[i] == j) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void apply_pivots_kernel(int n, int nrhs, const int* ipiv, double* B, int ldb) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n) return;
-  double* x = X + (size_t)col * ldx;
-  for (int i = 0; i < n; ++i) x[i] = (i == col) ? 1.0 : 0.0;
+  if (col >= nrhs) return;
+  double* b = B + (size_t)col * ldb;
   for (int c = 0; c < n; ++c) {
     const int p = ipiv[c];
-    if (p != c) { const double t = x[c]; x[c] = x[p]; x[p] = t; }
+    if (p != c) { const double t = b[c]; b[c] = b[p]; b[p] = t; }
   }
 }
 
@@ -347,14 +537,15 @@ __global__ void fro2_kernel(int m, int n, const double* A, int lda, double* part
   }
 }
 
-// Sum `ng` partials of each of `nq` quantities in a fixed order.
+// Sum `ng` partials of each of `nq` quantities in a fixed order (one wavefront per quantity).
 __global__ void finalize_kernel(const double* part, int ng, int nq, double* o0, double* o1, double* o2) {
-  const int q = threadIdx.x;
+  const int q = threadIdx.x / 64, lane = threadIdx.x % 64;
   if (q >= nq) return;
   double s = 0.0;
-  for (int g = 0; g < ng; ++g) s += part[q * RED_MAXG + g];
+  for (int g = lane; g < ng; g += 64) s += part[q * RED_MAXG + g];
+  s = wave_sum(s);
   double* o = q == 0 ? o0 : (q == 1 ? o1 : o2);
-  if (o) *o = s;
+  if (lane == 0 && o) *o = s;
 }
 
 int red_grid(size_t total) { return (int)std::max<size_t>(1, std::min<size_t>(RED_MAXG, (total + RED_WG * 4 - 1) / (RED_WG * 4))); }
@@ -362,6 +553,7 @@ int red_grid(size_t total) { return (int)std::max<size_t>(1, std::min<size_t>(RE
 }  // namespace
 
 int scratch_doubles() { return 3 * RED_MAXG; }
+int ipiv_ints(int n) { return 2 * n + 1 + 4 * NB + 8; }
 
 void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc, hipStream_t st) {
@@ -371,6 +563,8 @@ void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, 
     else if (beta != 1.0) throw Error(SKR_ENOTSUP, "gemm with k = 0 and beta != 0, 1");
     return;
   }
+  if (ta && !tb && run_gemm_splitk(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, alpha, beta, C, ldc, st)) return;
+  if (!ta && tb && run_gemm_splitk(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, alpha, beta, C, ldc, st)) return;
   if (!ta && !tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBN{B, ldb}, sc, st);
   else if (ta && !tb) run_gemm(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, sc, st);
   else if (!ta && tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, sc, st);
@@ -389,12 +583,25 @@ template void basis_gemm<float>(int, int, int, int, double, const float*, const 
 
 void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, hipStream_t st) {
   SKR_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int nb = std::min(NB, n - j0);
-    hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(PT), 0, st, n, A, lda, j0, nb, ipiv, info);
+  // the permutation lists of the panels live just past the 2n ints of ipiv
+  int* swaps = ipiv + 2 * (size_t)n;
+  static bool attr_set = false;
+  if (!attr_set) {
+    SKR_HIP(hipFuncSetAttribute((const void*)panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                PANEL_LDS_DOUBLES * (int)sizeof(double)));
+    attr_set = true;
+  }
+  // panel width: the widest power of two (<= NB) whose panel fits in LDS, NB otherwise
+  int pw = NB;
+  while (pw > 4 && (size_t)n * pw > PANEL_LDS_DOUBLES) pw /= 2;
+  if ((size_t)n * pw > PANEL_LDS_DOUBLES) pw = NB;
+  for (int j0 = 0; j0 < n; j0 += pw) {
+    const int nb = std::min(pw, n - j0);
+    const size_t lds = ((size_t)(n - j0) * nb <= PANEL_LDS_DOUBLES) ? (size_t)(n - j0) * nb * sizeof(double) : 0;
+    hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(PT), lds, st, n, A, lda, j0, nb, ipiv, info, swaps);
     check_launch("lu_panel");
     if (n - nb > 0) {
-      hipLaunchKernelGGL(laswp_kernel, dim3(ceil_div(n - nb, 256)), dim3(256), 0, st, n, A, lda, j0, nb, ipiv);
+      hipLaunchKernelGGL(laswp_kernel, dim3(ceil_div(n - nb, 256)), dim3(256), 0, st, n, A, lda, j0, nb, swaps);
       check_launch("laswp");
     }
     const int rest = n - j0 - nb;
@@ -412,21 +619,38 @@ void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, h
   }
 }
 
-void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st) {
-  hipLaunchKernelGGL(permuted_identity_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, ipiv, X, ldx);
-  check_launch("permuted_identity");
-  // X <- L^{-1} X (unit lower, forward)
+void trsm_left_lower_unit(int n, int nrhs, const double* L, int ldl, double* B, int ldb, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
   for (int b0 = 0; b0 < n; b0 += NB) {
     const int nb = std::min(NB, n - b0);
-    hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, nb,
-                       LU + b0 + (size_t)b0 * lda, lda, X + b0, ldx, n);
+    hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, st, nb,
+                       L + b0 + (size_t)b0 * ldl, ldl, B + b0, ldb, nrhs);
     check_launch("trsm_lln");
     const int below = n - b0 - nb;
     if (below > 0)
-      gemm(false, false, below, n, nb, -1.0, LU + (b0 + nb) + (size_t)b0 * lda, lda, X + b0, ldx, 1.0, X + b0 + nb,
-           ldx, st);
+      gemm(false, false, below, nrhs, nb, -1.0, L + (b0 + nb) + (size_t)b0 * ldl, ldl, B + b0, ldb, 1.0, B + b0 + nb,
+           ldb, st);
   }
+}
+
+void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st) {
+  // the permutation vector is kept just past the pivots (the caller's ipiv holds 2n ints)
+  int* perm = const_cast<int*>(ipiv) + n;
+  SKR_REQUIRE(n <= PERM_LDS, "matrix too large for the inverse");
+  hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(1024), 0, st, n, ipiv, perm);
+  check_launch("perm");
+  hipLaunchKernelGGL(permuted_identity_kernel, dim3(std::min(8192, ceil_div((int64_t)n * n, 256))), dim3(256), 0, st,
+                     n, perm, X, ldx);
+  check_launch("permuted_identity");
+  trsm_left_lower_unit(n, n, LU, lda, X, ldx, st);
   trsm_left_upper(n, n, LU, lda, X, ldx, st);
+}
+
+void getrs(int n, int nrhs, const double* LU, int lda, const int* ipiv, double* B, int ldb, hipStream_t st) {
+  hipLaunchKernelGGL(apply_pivots_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, st, n, nrhs, ipiv, B, ldb);
+  check_launch("apply_pivots");
+  trsm_left_lower_unit(n, nrhs, LU, lda, B, ldb, st);
+  trsm_left_upper(n, nrhs, LU, lda, B, ldb, st);
 }
 
 void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st) {
@@ -481,7 +705,7 @@ void newton_combine(int m, int n, const double* mu_dev, const double* X, int ldx
   const int g = red_grid((size_t)m * n);
   hipLaunchKernelGGL(combine_kernel, dim3(g), dim3(RED_WG), 0, st, m, n, mu_dev, X, ldx, Y, ldy, Z, ldz, scratch);
   check_launch("newton_combine");
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, scratch, g, 3, diff_dev, norm_dev, trace_dev);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(192), 0, st, scratch, g, 3, diff_dev, norm_dev, trace_dev);
   check_launch("finalize");
 }
 

@@ -126,14 +126,23 @@ __global__ void aca_select_kernel(int m, int ng, const double* R, double* Y1, do
   __shared__ double pv;
   __shared__ int stop;
   if (state[1]) return;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {  // one wavefront reduces the partials (fixed order)
+    const int lane = threadIdx.x;
     double b = -1.0, s2 = 0.0;
     long long bi = -1;
     const long long* ip = reinterpret_cast<const long long*>(ipart);
-    for (int g = 0; g < ng; ++g) {
+    for (int g = lane; g < ng; g += 64) {
       s2 += part[ACA_G + g];
       if (part[g] > b || (part[g] == b && ip[g] >= 0 && (bi < 0 || ip[g] < bi))) { b = part[g]; bi = ip[g]; }
     }
+    s2 = wave_sum(s2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(b, off, 64);
+      const long long oi = __shfl_xor(bi, off, 64);
+      if (ob > b || (ob == b && oi >= 0 && (bi < 0 || oi < bi))) { b = ob; bi = oi; }
+    }
+    if (lane == 0) {
     const int k = state[0];
     if (k == 0) *ynorm2 = s2;
     stop = (k >= kmax) || !(b > 0.0) || bi < 0 || (s2 <= tol2 * *ynorm2);
@@ -141,6 +150,7 @@ __global__ void aca_select_kernel(int m, int ng, const double* R, double* Y1, do
     pi = (int)(bi % m);
     pj = (int)(bi / m);
     pv = stop ? 1.0 : R[(size_t)pi + (size_t)pj * m];
+    }
   }
   __syncthreads();
   if (stop) return;
@@ -153,6 +163,256 @@ __global__ void aca_select_kernel(int m, int ng, const double* R, double* Y1, do
   if (threadIdx.x == 0) state[0] = k + 1;
 }
 
+// ---- spectral deflation of the sign-function solve --------------------------------
+// With S_A = sign(A), S_B = sign(B) (the limits of the coupled iteration) its C-limit W
+// solves A W + W B = S_A F + F S_B, i.e. W = S_A Y + Y S_B, hence
+//     Y = W/2 + P_A Y + Y P_B,   P = (I - S)/2 the spectral projector on the eigenvalues
+// in the open left half plane.  Y P_B = Z L^T with P_B = R L^T (R orthonormal, q_B
+// columns) and A Z + Z (R^T B R) = F R, a Sylvester equation with a q_B x q_B right
+// coefficient solved through its complex Schur form and q_B shifted solves with A.
+// P_A Y follows from the transposed equation.
+
+// P = 0.5 (I - S) or 0.5 (I - S^T)
+__global__ void half_i_minus_kernel(int m, const double* S, int lds, int trans, double* P) {
+  const size_t total = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double sv = trans ? S[j + (size_t)i * lds] : S[i + (size_t)j * lds];
+    P[e] = 0.5 * ((i == j ? 1.0 : 0.0) - sv);
+  }
+}
+
+__device__ inline uint64_t hash64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// m x q test matrix with entries uniform in [-1, 1)
+__global__ void omega_kernel(int m, int q, uint64_t seed, double* O) {
+  const size_t total = (size_t)m * q;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t z = hash64(seed + (e + 1) * 0x9E3779B97F4A7C15ull);
+    O[e] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+// Orthonormalise the columns of the m x q column-major G in place (classical Gram-Schmidt,
+// two passes).  One workgroup.  info = 1 if a column loses more than 1 - 1e-10 of its norm.
+__global__ void orth_kernel(int m, int q, double* G, int* info) {
+  __shared__ double red[1024 / 64];
+  __shared__ double coef[64];
+  const int tid = threadIdx.x;
+  auto wg_sum = [&](double v) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (tid % 64 == 0) red[tid / 64] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) t += red[w];
+    return t;
+  };
+  for (int j = 0; j < q; ++j) {
+    double* gj = G + (size_t)j * m;
+    const double n0 = sqrt(wg_sum([&] { double a = 0.0; for (int i = tid; i < m; i += blockDim.x) a += gj[i] * gj[i]; return a; }()));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int k = 0; k < j; ++k) {
+        const double* gk = G + (size_t)k * m;
+        double a = 0.0;
+        for (int i = tid; i < m; i += blockDim.x) a += gk[i] * gj[i];
+        const double c = wg_sum(a);
+        if (tid == 0) coef[k] = c;
+      }
+      __syncthreads();
+      for (int i = tid; i < m; i += blockDim.x) {
+        double t = gj[i];
+        for (int k = 0; k < j; ++k) t -= coef[k] * G[(size_t)k * m + i];
+        gj[i] = t;
+      }
+      __syncthreads();
+    }
+    const double n1 = sqrt(wg_sum([&] { double a = 0.0; for (int i = tid; i < m; i += blockDim.x) a += gj[i] * gj[i]; return a; }()));
+    if (!(n1 > 1e-10 * n0)) {
+      if (tid == 0) *info = 1;
+      return;
+    }
+    for (int i = tid; i < m; i += blockDim.x) gj[i] /= n1;
+    __syncthreads();
+  }
+}
+
+// RHS (m x q) = F R with F zero outside its top-left r x r block F(i, a) = F11[i r + a]
+// (or F11[a r + i] for the transposed equation).
+__global__ void rhs_proj_kernel(int m, int q, int r, const double* F11, int ft, const double* R, double* RHS) {
+  const size_t total = (size_t)m * q;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    double t = 0.0;
+    if (i < r)
+      for (int a = 0; a < r; ++a) t += (ft ? F11[a * r + i] : F11[i * r + a]) * R[a + (size_t)c * m];
+    RHS[e] = t;
+  }
+}
+
+struct cx {
+  double re, im;
+};
+__device__ inline cx cmk(double a, double b) { return {a, b}; }
+__device__ inline cx cadd(cx a, cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cx csub(cx a, cx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cx cmul(cx a, cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cx cconj(cx a) { return {a.re, -a.im}; }
+__device__ inline double cabs2(cx a) { return hypot(a.re, a.im); }
+__device__ inline cx cscale(cx a, double s) { return {a.re * s, a.im * s}; }
+__device__ inline cx csqrt2(cx z) {
+  const double r = cabs2(z);
+  double a = sqrt(0.5 * (r + z.re)), b = sqrt(0.5 * fmax(r - z.re, 0.0));
+  if (z.im < 0) b = -b;
+  return {a, b};
+}
+
+// Complex Schur form B = Q T Q^H of a small real q x q matrix (column-major), single thread:
+// Householder reduction to Hessenberg form, then implicit single-shift QR sweeps with
+// Wilkinson shifts and deflation.  T, Q are returned as real/imaginary parts.
+__global__ void schur_kernel(int q, const double* B, double* Tre, double* Tim, double* Qre, double* Qim, int* info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  auto H = [&](int i, int j) -> cx { return cmk(Tre[i + j * q], Tim[i + j * q]); };
+  auto setH = [&](int i, int j, cx v) { Tre[i + j * q] = v.re; Tim[i + j * q] = v.im; };
+  auto Q = [&](int i, int j) -> cx { return cmk(Qre[i + j * q], Qim[i + j * q]); };
+  auto setQ = [&](int i, int j, cx v) { Qre[i + j * q] = v.re; Qim[i + j * q] = v.im; };
+  for (int j = 0; j < q; ++j)
+    for (int i = 0; i < q; ++i) {
+      Tre[i + j * q] = B[i + j * q];
+      Tim[i + j * q] = 0.0;
+      Qre[i + j * q] = (i == j) ? 1.0 : 0.0;
+      Qim[i + j * q] = 0.0;
+    }
+  // real Householder reduction to upper Hessenberg form
+  double v[64];
+  for (int k = 0; k + 2 < q; ++k) {
+    double nrm2 = 0.0;
+    for (int i = k + 1; i < q; ++i) { v[i] = Tre[i + k * q]; nrm2 += v[i] * v[i]; }
+    const double nrm = sqrt(nrm2);
+    if (nrm == 0.0) continue;
+    const double alpha = v[k + 1] >= 0 ? -nrm : nrm;
+    v[k + 1] -= alpha;
+    double vv = 0.0;
+    for (int i = k + 1; i < q; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    for (int j = 0; j < q; ++j) {  // rows k+1.. of H
+      double t = 0.0;
+      for (int i = k + 1; i < q; ++i) t += v[i] * Tre[i + j * q];
+      t *= beta;
+      for (int i = k + 1; i < q; ++i) Tre[i + j * q] -= t * v[i];
+    }
+    for (int i = 0; i < q; ++i) {  // columns k+1.. of H and of Q
+      double t = 0.0, u = 0.0;
+      for (int j = k + 1; j < q; ++j) { t += Tre[i + j * q] * v[j]; u += Qre[i + j * q] * v[j]; }
+      t *= beta;
+      u *= beta;
+      for (int j = k + 1; j < q; ++j) { Tre[i + j * q] -= t * v[j]; Qre[i + j * q] -= u * v[j]; }
+    }
+  }
+  const double eps = 2.220446049250313e-16;
+  int hi = q - 1, its = 0;
+  while (hi > 0) {
+    int l = 0;
+    for (int k = hi; k >= 1; --k) {
+      const double sub = cabs2(H(k, k - 1));
+      if (sub <= eps * (cabs2(H(k, k)) + cabs2(H(k - 1, k - 1))) || sub == 0.0) {
+        setH(k, k - 1, cmk(0, 0));
+        l = k;
+        break;
+      }
+    }
+    if (l == hi) { --hi; its = 0; continue; }
+    if (++its > 100) { *info = 2; return; }
+    const cx a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+    const cx half_tr = cscale(cadd(a, d), 0.5), dd = cscale(csub(a, d), 0.5);
+    const cx disc = csqrt2(cadd(cmul(dd, dd), cmul(b, c)));
+    const cx mu1 = cadd(half_tr, disc), mu2 = csub(half_tr, disc);
+    cx mu = cabs2(csub(mu1, d)) < cabs2(csub(mu2, d)) ? mu1 : mu2;
+    if (its % 11 == 10) mu = cadd(d, cmk(cabs2(c), 0.0));  // exceptional shift
+    cx x = csub(H(l, l), mu), y = H(l + 1, l);
+    for (int k = l; k < hi; ++k) {
+      const double ax = cabs2(x), ay = cabs2(y), nrm = hypot(ax, ay);
+      double cc;
+      cx ss;
+      if (nrm == 0.0) { cc = 1.0; ss = cmk(0, 0); }
+      else if (ax == 0.0) { cc = 0.0; ss = cscale(cconj(y), 1.0 / ay); }
+      else { cc = ax / nrm; ss = cscale(cmul(cscale(x, 1.0 / ax), cconj(y)), 1.0 / nrm); }
+      for (int j = (k > l ? k - 1 : l); j < q; ++j) {  // rows k, k+1
+        const cx h1 = H(k, j), h2 = H(k + 1, j);
+        setH(k, j, cadd(cscale(h1, cc), cmul(ss, h2)));
+        setH(k + 1, j, csub(cscale(h2, cc), cmul(cconj(ss), h1)));
+      }
+      const int imax = min(k + 2, hi);
+      for (int i = 0; i <= imax; ++i) {  // columns k, k+1
+        const cx h1 = H(i, k), h2 = H(i, k + 1);
+        setH(i, k, cadd(cscale(h1, cc), cmul(h2, cconj(ss))));
+        setH(i, k + 1, csub(cscale(h2, cc), cmul(h1, ss)));
+      }
+      for (int i = 0; i < q; ++i) {
+        const cx q1 = Q(i, k), q2 = Q(i, k + 1);
+        setQ(i, k, cadd(cscale(q1, cc), cmul(q2, cconj(ss))));
+        setQ(i, k + 1, csub(cscale(q2, cc), cmul(q1, ss)));
+      }
+      if (k < hi - 1) { x = H(k + 1, k); y = H(k + 2, k); }
+    }
+  }
+  for (int j = 0; j < q; ++j)
+    for (int i = j + 1; i < q; ++i) { Tre[i + j * q] = 0.0; Tim[i + j * q] = 0.0; }
+}
+
+// rhs2 = [Re; Im] of Rt[:, j] - sum_{i<j} Zt[:, i] T(i, j)
+__global__ void cplx_rhs_kernel(int m, int j, int q, const double* Rtre, const double* Rtim, const double* Zre,
+                                const double* Zim, const double* Tre, const double* Tim, double* rhs2) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    double re = Rtre[e + (size_t)j * m], im = Rtim[e + (size_t)j * m];
+    for (int i = 0; i < j; ++i) {
+      const double zr = Zre[e + (size_t)i * m], zi = Zim[e + (size_t)i * m];
+      const double tr = Tre[i + j * q], ti = Tim[i + j * q];
+      re -= zr * tr - zi * ti;
+      im -= zr * ti + zi * tr;
+    }
+    rhs2[e] = re;
+    rhs2[m + e] = im;
+  }
+}
+
+// K (2m x 2m) = [[A + a I, -b I], [b I, A + a I]] with a + ib = T(j, j)
+__global__ void build_shift_kernel(int m, const double* A, int lda, const double* Tre, const double* Tim, int q, int j,
+                                   double* K) {
+  const double a = Tre[j + j * q], b = Tim[j + j * q];
+  const int n2 = 2 * m;
+  const size_t total = (size_t)n2 * n2;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n2), k = (int)(e / n2);
+    const int bi = i / m, bk = k / m, ii = i % m, kk = k % m;
+    double v;
+    if (bi == bk) v = A[ii + (size_t)kk * lda] + (ii == kk ? a : 0.0);
+    else v = (ii == kk) ? (bi == 0 ? -b : b) : 0.0;
+    K[e] = v;
+  }
+}
+
+__global__ void split_kernel(int m, int j, const double* x, double* Zre, double* Zim) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+    Zre[e + (size_t)j * m] = x[e];
+    Zim[e + (size_t)j * m] = x[m + e];
+  }
+}
+
+// Y += G (or G^T)
+__global__ void add_kernel(int m, const double* G, int trans, double* Y) {
+  const size_t total = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    Y[e] += trans ? G[j + (size_t)i * m] : G[e];
+  }
+}
+
 }  // namespace
 
 ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st_(st) {
@@ -160,10 +420,22 @@ ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st
   mbar_u_.alloc((size_t)(mmax + r) * mmax);
   mbar_v_.alloc((size_t)(mmax + r) * mmax);
   a_.alloc(mm); b_.alloc(mm); ai_.alloc(mm); bi_.alloc(mm); c_.alloc(mm); w1_.alloc(mm); w2_.alloc(mm); lu_.alloc(mm);
-  ipiv_.alloc(mmax);
+  ipiv_.alloc(dense::ipiv_ints(mmax));
+  ipivb_.alloc(dense::ipiv_ints(mmax));
+  lub_.alloc(mm);
   info_.alloc(2);
   scal_.alloc(SCAL_N);
   scratch_.alloc(dense::scratch_doubles());
+  SKR_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+  SKR_HIP(hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming));
+  SKR_HIP(hipEventCreateWithFlags(&ev_aux_, hipEventDisableTiming));
+}
+
+ProjSolver::~ProjSolver() {
+  if (aux_) (void)hipStreamSynchronize(aux_);
+  if (ev_main_) (void)hipEventDestroy(ev_main_);
+  if (ev_aux_) (void)hipEventDestroy(ev_aux_);
+  if (aux_) (void)hipStreamDestroy(aux_);
 }
 
 void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar) {
@@ -177,6 +449,81 @@ void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar) {
   }
   // Mbar <- Mbar T_d^{-1}
   dense::trsm_right_upper(m + r_, m, sp.T, ld, Mbar, ldm, st_);
+}
+
+constexpr int QMAX = 64;  // largest deflated subspace handled
+
+void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* Mst, int lms, const double* S,
+                               int s_trans, const double* F11, int f_trans, int q, double* G) {
+  SKR_REQUIRE(q >= 1 && q <= QMAX, "deflated subspace too large");
+  const size_t mq = (size_t)m * q;
+  if (!dws_.p || dws_.n < 12 * (size_t)mmax_ * QMAX) dws_.alloc(12 * (size_t)mmax_ * QMAX + 8 * QMAX * QMAX);
+  double* P = ai_.p;  // m x m
+  double* O = dws_.p;
+  double* R = O + mq;
+  double* BR = R + mq;
+  double* RHS = BR + mq;
+  double* Rtre = RHS + mq;
+  double* Rtim = Rtre + mq;
+  double* Zre = Rtim + mq;
+  double* Zim = Zre + mq;
+  double* Lt = Zim + mq;       // q x m
+  double* Zr = Lt + mq;        // m x q (real Z)
+  double* rhs2 = Zr + mq;      // 2m
+  double* Bq = rhs2 + 2 * (size_t)m;
+  double* Tre = Bq + q * q;
+  double* Tim = Tre + q * q;
+  double* Qre = Tim + q * q;
+  double* Qim = Qre + q * q;
+  const int g = std::min(4096, ceil_div((int64_t)m * m, 256));
+  hipLaunchKernelGGL(half_i_minus_kernel, dim3(g), dim3(256), 0, st_, m, S, m, s_trans, P);
+  check_launch("half_i_minus");
+  hipLaunchKernelGGL(omega_kernel, dim3(std::min(1024, ceil_div((int64_t)mq, 256))), dim3(256), 0, st_, m, q,
+                     (uint64_t)0x5EED0000ull + (uint64_t)q, O);
+  check_launch("omega");
+  dense::gemm(false, false, m, q, m, 1.0, P, m, O, m, 0.0, R, m, st_);
+  SKR_HIP(hipMemsetAsync(info_.p, 0, 2 * sizeof(int), st_));
+  hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st_, m, q, R, info_.p);
+  check_launch("orth");
+  dense::gemm(true, false, m, q, m, 1.0, Mst, lms, R, m, 0.0, BR, m, st_);     // B R = Mst^T R
+  dense::gemm(true, false, q, q, m, 1.0, R, m, BR, m, 0.0, Bq, q, st_);        // R^T B R
+  dense::gemm(true, false, q, m, m, 1.0, R, m, P, m, 0.0, Lt, q, st_);         // L^T = R^T P
+  hipLaunchKernelGGL(rhs_proj_kernel, dim3(std::min(1024, ceil_div((int64_t)mq, 256))), dim3(256), 0, st_, m, q, r_,
+                     F11, f_trans, R, RHS);
+  check_launch("rhs_proj");
+  hipLaunchKernelGGL(schur_kernel, dim3(1), dim3(1), 0, st_, q, Bq, Tre, Tim, Qre, Qim, info_.p + 1);
+  check_launch("schur");
+  int hinfo[2];
+  SKR_HIP(hipMemcpyAsync(hinfo, info_.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
+  SKR_HIP(hipStreamSynchronize(st_));
+  if (hinfo[0]) throw Error(SKR_EPROJ, "rank loss in the deflated spectral subspace");
+  if (hinfo[1]) throw Error(SKR_EPROJ, "small Schur decomposition did not converge");
+  dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qre, q, 0.0, Rtre, m, st_);
+  dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qim, q, 0.0, Rtim, m, st_);
+  const int n2 = 2 * m;
+  if (!kbuf_.p || kbuf_.n < (size_t)n2 * n2) {
+    kbuf_.alloc((size_t)4 * mmax_ * mmax_);
+    ipiv2_.alloc(dense::ipiv_ints(2 * mmax_));
+  }
+  for (int j = 0; j < q; ++j) {
+    hipLaunchKernelGGL(cplx_rhs_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, q, Rtre, Rtim,
+                       Zre, Zim, Tre, Tim, rhs2);
+    check_launch("cplx_rhs");
+    hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0, st_,
+                       m, Al, lal, Tre, Tim, q, j, kbuf_.p);
+    check_launch("build_shift");
+    dense::getrf(n2, kbuf_.p, n2, ipiv2_.p, info_.p, nullptr, st_);
+    dense::getrs(n2, 1, kbuf_.p, n2, ipiv2_.p, rhs2, n2, st_);
+    hipLaunchKernelGGL(split_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, rhs2, Zre, Zim);
+    check_launch("split");
+  }
+  SKR_HIP(hipMemcpyAsync(hinfo, info_.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+  SKR_HIP(hipStreamSynchronize(st_));
+  if (hinfo[0]) throw Error(SKR_EPROJ, "singular shifted system in the deflated solve");
+  // Z = Re(Zt Q^H) = Zre Qre^T + Zim Qim^T ;  G = Z L^T
+  dense::gemm(false, true, m, q, q, 1.0, Zre, m, Qre, q, 0.0, Zr, m, st_);
+  dense::gemm(false, true, m, q, q, 1.0, Zim, m, Qim, q, 1.0, Zr, m, st_);
+  dense::gemm(false, false, m, m, q, 1.0, Zr, m, Lt, q, 0.0, G, m, st_);
 }
 
 double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const double* F11, ProjStats* stats) {
@@ -199,12 +546,17 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   std::vector<double> hs(SCAL_N);
   int hinfo[2];
   for (it = 0; it < maxit; ++it) {
+    // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
+    SKR_HIP(hipEventRecord(ev_main_, st_));
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
+    dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
+    dense::getrf(m, lub_.p, m, ipivb_.p, info_.p + 1, s + LDB, aux_);
+    dense::getri(m, lub_.p, m, ipivb_.p, bi_.p, m, aux_);
+    SKR_HIP(hipEventRecord(ev_aux_, aux_));
     dense::copy(m, m, a_.p, m, lu_.p, m, st_);
     dense::getrf(m, lu_.p, m, ipiv_.p, info_.p, s + LDA, st_);
     dense::getri(m, lu_.p, m, ipiv_.p, ai_.p, m, st_);
-    dense::copy(m, m, b_.p, m, lu_.p, m, st_);
-    dense::getrf(m, lu_.p, m, ipiv_.p, info_.p + 1, s + LDB, st_);
-    dense::getri(m, lu_.p, m, ipiv_.p, bi_.p, m, st_);
+    SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
     hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
     check_launch("mu");
     dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
@@ -221,10 +573,12 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     if (!std::isfinite(rel))
       throw Error(SKR_EPROJ, "non-finite sign iteration (d = " + std::to_string(d) + ")");
     if (rel < 1e-2) scale = false;
+    // quadratic convergence: a change below 1e-10 leaves the new iterate at rounding level
+    if (rel < 1e-10) { ++it; break; }
     if (extra >= 0) {
       if (--extra < 0) { ++it; break; }
-    } else if (rel < 1e-10 || (rel < 1e-6 && rel > 0.5 * prev)) {
-      extra = 1;  // quadratic convergence: one more step reaches rounding level
+    } else if (rel < 1e-6 && rel > 0.5 * prev) {
+      extra = 1;  // stagnation at rounding level
     }
     prev = rel;
   }
@@ -235,16 +589,28 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     stats->neg_eigs_b = qb;
   }
   if (it >= maxit) throw Error(SKR_EPROJ, "sign iteration did not converge (d = " + std::to_string(d) + ")");
-  if (qa != 0 || qb != 0)
-    throw Error(SKR_EPROJ, "projected matrices have eigenvalues in the left half plane (" + std::to_string(qa) + ", " +
-                               std::to_string(qb) + ") at d = " + std::to_string(d) +
-                               "; the sign-function solver needs positive real spectra");
+  if (qa < 0 || qb < 0 || qa > QMAX || qb > QMAX)
+    throw Error(SKR_EPROJ, "projected matrices have too many eigenvalues in the left half plane (" +
+                               std::to_string(qa) + ", " + std::to_string(qb) + ") at d = " + std::to_string(d));
   // Y = C / 2:  (mu X + 0 / mu) / 2 with mu = 1
   hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, 1.0);
   check_launch("set_scalar");
   dense::copy(m, m, c_.p, m, w1_.p, m, st_);
   dense::set_zero(m, m, w2_.p, m, st_);
   dense::newton_combine(m, m, s + MU, w1_.p, m, w2_.p, m, c_.p, m, s + DC, s + YN2, nullptr, scratch_.p, st_);
+  // eigenvalues in the left half plane: Y = W/2 + P_A Y + Y P_B
+  if (qb > 0) {  // Y P_B with A = M_A, B = M_B^T
+    deflate_right(m, mbar_u_.p, ldm, mbar_v_.p, ldm, b_.p, 0, F11, 0, qb, bi_.p);
+    hipLaunchKernelGGL(add_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, bi_.p, 0,
+                       c_.p);
+    check_launch("add");
+  }
+  if (qa > 0) {  // (P_A Y)^T = Y^T P_{A^T}: transposed equation M_B Y^T + Y^T M_A^T = F^T
+    deflate_right(m, mbar_v_.p, ldm, mbar_u_.p, ldm, a_.p, 1, F11, 1, qa, bi_.p);
+    hipLaunchKernelGGL(add_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, bi_.p, 1,
+                       c_.p);
+    check_launch("add");
+  }
   // projected residual ||M_A Y + Y M_B^T - F||_F / ||F||_F (diagnostic)
   dense::gemm(false, false, m, m, m, 1.0, mbar_u_.p, ldm, c_.p, m, 0.0, w1_.p, m, st_);
   dense::gemm(false, true, m, m, m, 1.0, c_.p, m, mbar_v_.p, ldm, 1.0, w1_.p, m, st_);
@@ -257,7 +623,10 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   check_launch("rho");
   SKR_HIP(hipMemcpyAsync(hs.data(), s, SCAL_N * sizeof(double), hipMemcpyDeviceToHost, st_));
   SKR_HIP(hipStreamSynchronize(st_));
-  if (stats) stats->proj_resid = std::sqrt(hs[RES2] / hs[F2]);
+  const double pres = std::sqrt(hs[RES2] / hs[F2]);
+  if (stats) stats->proj_resid = pres;
+  if (!(pres <= 1e-6))
+    throw Error(SKR_EPROJ, "projected Sylvester residual " + std::to_string(pres) + " at d = " + std::to_string(d));
   return std::sqrt(hs[RHO2]);
 }
 

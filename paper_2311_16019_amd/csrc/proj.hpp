@@ -28,6 +28,9 @@ struct ProjStats {
 class ProjSolver {
  public:
   ProjSolver(int r, int mmax, hipStream_t st);
+  ~ProjSolver();
+  ProjSolver(const ProjSolver&) = delete;
+  ProjSolver& operator=(const ProjSolver&) = delete;
   // Solve at block step d (m = d r).  F11 is the device r x r block beta_1 beta_2^T
   // (row-major).  Returns rho (absolute).  Throws Error(SKR_EPROJ) when the projected
   // equation cannot be solved by the sign iteration.
@@ -43,12 +46,21 @@ class ProjSolver {
 
  private:
   void form(int d, const ProjSpace& sp, double* Mbar);
+  // G = Y P_-(B) for A Y + Y B = F given Al = A (ld lal), B = Mst^T (Mst ld lms), the sign
+  // S of B (or of B^T when s_trans) and F from F11 (transposed when f_trans); q = rank P_-.
+  void deflate_right(int m, const double* Al, int lal, const double* Mst, int lms, const double* S, int s_trans,
+                     const double* F11, int f_trans, int q, double* G);
   int r_, mmax_, m_ = 0;
   hipStream_t st_;
+  hipStream_t aux_ = nullptr;  // second stream: the two inversions of a Newton step overlap
+  hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr;
+  DBuf<double> lub_;
+  DBuf<int> ipivb_;
   DBuf<double> mbar_u_, mbar_v_, a_, b_, ai_, bi_, c_, w1_, w2_, lu_, y1_, y2_;
   DBuf<int> ipiv_, info_;
   DBuf<double> scal_, scratch_;
-  DBuf<double> acapart_;
+  DBuf<double> acapart_, dws_, kbuf_;
+  DBuf<int> ipiv2_;
   DBuf<int> acaint_;
 };
 

@@ -90,6 +90,53 @@ int step_wgs(int n) {
   return std::max(8, std::min(1024, g));
 }
 
+// HIP-event timing of kernel families on the solve's stream (enabled by params.profile).
+class Profiler {
+ public:
+  Profiler(bool on, hipStream_t st) : on_(on), st_(st) {}
+  ~Profiler() {
+    for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool_) (void)hipEventDestroy(e);
+  }
+  void begin(int fam) {
+    if (!on_) return;
+    cur_ = {get(), nullptr, fam};
+    SKR_HIP(hipEventRecord(cur_.a, st_));
+  }
+  void end() {
+    if (!on_) return;
+    cur_.b = get();
+    SKR_HIP(hipEventRecord(cur_.b, st_));
+    pending_.push_back(cur_);
+  }
+  // call after the stream has been synchronised
+  void resolve(skr_result_s* res) {
+    for (auto& p : pending_) {
+      float ms = 0.f;
+      SKR_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      res->fam_launches[p.fam] += 1;
+      res->fam_ms[p.fam] += ms;
+      pool_.push_back(p.a);
+      pool_.push_back(p.b);
+    }
+    pending_.clear();
+  }
+
+ private:
+  struct Pair { hipEvent_t a, b; int fam; };
+  hipEvent_t get() {
+    if (!pool_.empty()) { hipEvent_t e = pool_.back(); pool_.pop_back(); return e; }
+    hipEvent_t e;
+    SKR_HIP(hipEventCreate(&e));
+    return e;
+  }
+  bool on_;
+  hipStream_t st_;
+  Pair cur_{};
+  std::vector<Pair> pending_;
+  std::vector<hipEvent_t> pool_;
+};
+
 template <typename T>
 struct Space {
   CsrView<T> A;
@@ -98,7 +145,6 @@ struct Space {
   bool stored = true;
   DBuf<T> basis, work;
   DBuf<double> H, Tm, Q, small, part, skpart, w, c1, c2, wpart, ell;
-  DBuf<unsigned> counter;
   DBuf<int> broken;
   DBuf<uint16_t> tab;
   T* slot(int j) const {  // 1-based basis block j
@@ -112,7 +158,7 @@ template <typename T>
 class Solver {
  public:
   Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
-      : r_(r), p_(p), st_(st) {
+      : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
     SKR_REQUIRE(r >= 1 && r <= RMAX, "r must be in [1, 16]");
     SKR_REQUIRE(p.k >= 1, "k must be >= 1");
     SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
@@ -175,6 +221,7 @@ class Solver {
         float ms = 0.f;
         SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
         res->ms_steps += ms;
+        prof_.resolve(res.get());
         const int db = std::min(hb[0], hb[1]);
         const int dc = std::min(d, db);
         const bool broke = db <= d;
@@ -240,7 +287,6 @@ class Solver {
     s.Q.alloc((size_t)s_ * ld_);
     s.small.alloc(SmallLayout::SIZE);
     s.part.alloc((size_t)s.nwg * (RMAX * RMAX + 8));
-    s.counter.alloc(1);
     s.broken.alloc(1);
     s.nchunk = sketch_chunks(s.n);
     s.skpart.alloc((size_t)s.nchunk * s_ * r_);
@@ -253,7 +299,6 @@ class Solver {
     s.H.zero(st_);
     s.Tm.zero(st_);
     s.small.zero(st_);
-    s.counter.zero(st_);
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st_, s.broken.p, INT_MAX);
     check_launch("fill_int");
   }
@@ -264,7 +309,6 @@ class Solver {
     a.Y = s.work.p;
     a.small = s.small.p;
     a.part = s.part.p;
-    a.counter = s.counter.p;
     a.broken = s.broken.p;
     a.ldh = ld_;
     a.n = s.n;
@@ -347,7 +391,9 @@ class Solver {
       a[q].post = POST_DOT;
       a[q].Hblk = Hblk(s, i0, d);
     }
+    prof_.begin(KF_SPMM);
     launch_spmm_dot<T>(r_, a[0], a[1], st_);
+    prof_.end();
     for (int i = i0; i <= d; ++i) {
       for (int q = 0; q < 2; ++q) {
         Space<T>& s = sp_[q];
@@ -362,19 +408,29 @@ class Solver {
           a[q].Hblk = (r_ == 1) ? Hblk(s, d + 1, d) : nullptr;
         }
       }
+      prof_.begin(KF_AXPY);
       launch_axpy_reduce<T>(r_, a[0], a[1], st_);
+      prof_.end();
     }
     if (r_ > 1) {
       for (int q = 0; q < 2; ++q) {
         a[q].post = POST_GRAM2;
         a[q].Hblk = Hblk(sp_[q], d + 1, d);
       }
+      prof_.begin(KF_GRAM2);
       launch_gram2<T>(r_, a[0], a[1], st_);
+      prof_.end();
     }
     for (int q = 0; q < 2; ++q) a[q].Unew = sp_[q].slot(d + 1);
+    prof_.begin(KF_NORMALIZE);
     launch_normalize<T>(r_, a[0], a[1], st_);
+    prof_.end();
+    prof_.begin(KF_SKETCH);
     sketch(d + 1);
+    prof_.end();
+    prof_.begin(KF_WHITEN);
     whiten(d, d);
+    prof_.end();
   }
 
   // Two-pass recovery: regenerate U_1..U_d from C and the stored H (no inner products) and
@@ -459,6 +515,7 @@ class Solver {
   int ld_ = 0;
   size_t lds_limit_ = 65536;
   Space<T> sp_[2];
+  Profiler prof_;
   DBuf<double> F11_;
   std::vector<double> rhs_block_host_;
 };

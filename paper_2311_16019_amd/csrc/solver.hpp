@@ -6,7 +6,17 @@
 #include "op.hpp"
 #include "proj.hpp"
 
+namespace skr {
+enum KernelFamily { KF_SPMM = 0, KF_AXPY, KF_GRAM2, KF_NORMALIZE, KF_SKETCH, KF_WHITEN, KF_COUNT };
+inline const char* kernel_family_name(int f) {
+  static const char* names[KF_COUNT] = {"spmm_dot", "axpy_reduce", "gram2", "normalize", "sketch", "whiten"};
+  return (f >= 0 && f < KF_COUNT) ? names[f] : "";
+}
+}  // namespace skr
+
 struct skr_result_s {
+  int64_t fam_launches[skr::KF_COUNT] = {};
+  double fam_ms[skr::KF_COUNT] = {};
   int64_t n1 = 0, n2 = 0, ell = 0;
   int32_t iters = 0, status = 0;
   double rho_rel = 0.0;

@@ -8,13 +8,16 @@
 namespace skr {
 namespace {
 
-constexpr int JB = 4;        // columns of Q per workgroup in Q^T w
 constexpr int WT = 256;      // threads for the streaming whitening kernels
 constexpr int FT = 1024;     // threads of the finishing workgroup
 constexpr int SPLIT_COLS = 128;
 
 template <int R>
+constexpr int jb_of() { return R <= 4 ? 8 : (R <= 8 ? 4 : 2); }
+
+template <int R>
 __global__ void __launch_bounds__(WT) qtw_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
+  constexpr int JB = jb_of<R>();
   const WhitenSpace& a = blockIdx.y ? a1 : a0;
   const int j0 = blockIdx.x * JB;
   double acc[JB][R];
@@ -26,15 +29,13 @@ __global__ void __launch_bounds__(WT) qtw_kernel(WhitenSpace a0, WhitenSpace a1,
     double wr[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) wr[c] = a.w[(size_t)i * R + c];
+    double q[JB];
 #pragma unroll
-    for (int jb = 0; jb < JB; ++jb) {
-      const int j = j0 + jb;
-      if (j < m) {
-        const double q = a.Q[(size_t)j * s + i];
+    for (int jb = 0; jb < JB; ++jb) q[jb] = (j0 + jb < m) ? a.Q[(size_t)(j0 + jb) * s + i] : 0.0;
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[jb][c] += q * wr[c];
-      }
-    }
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[jb][c] += q[jb] * wr[c];
   }
   __shared__ double red[WT / 64][JB * R];
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
@@ -63,15 +64,28 @@ __global__ void __launch_bounds__(WT) qc_part_kernel(WhitenSpace a0, WhitenSpace
   const WhitenSpace& a = blockIdx.z ? a1 : a0;
   const int i = blockIdx.x * WT + threadIdx.x;
   const int j0 = blockIdx.y * cols_per_split, j1 = min(m, j0 + cols_per_split);
-  if (i >= s) return;
+  extern __shared__ double cs[];  // the split's rows of c, staged once per workgroup
   const double* c = which ? a.c2 : a.c1;
+  for (int e = threadIdx.x; e < (j1 - j0) * R; e += WT) cs[e] = c[(size_t)j0 * R + e];
+  __syncthreads();
+  if (i >= s) return;
   double acc[R];
 #pragma unroll
   for (int cc = 0; cc < R; ++cc) acc[cc] = 0.0;
-  for (int j = j0; j < j1; ++j) {
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    double q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = a.Q[(size_t)(j + u) * s + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cc = 0; cc < R; ++cc) acc[cc] += q[u] * cs[(j + u - j0) * R + cc];
+  }
+  for (; j < j1; ++j) {
     const double q = a.Q[(size_t)j * s + i];
 #pragma unroll
-    for (int cc = 0; cc < R; ++cc) acc[cc] += q * c[(size_t)j * R + cc];
+    for (int cc = 0; cc < R; ++cc) acc[cc] += q * cs[(j - j0) * R + cc];
   }
 #pragma unroll
   for (int cc = 0; cc < R; ++cc) a.part[((size_t)blockIdx.y * s + i) * R + cc] = acc[cc];
@@ -117,23 +131,53 @@ __device__ void inv_upper_small(const double* U, double* V, int r) {
 }
 
 // Gram matrix of the s x R row-major block w, reduced over the workgroup into G (LDS).
+// Small R: every thread accumulates the full R x R outer products of its rows (independent
+// loads), then a wavefront + LDS reduction; large R: threads own (a, b) pairs.
 template <int R>
 __device__ void wg_gram(const double* w, int s, double* G, double* red) {
-  constexpr int RR = R * R, PH = FT / RR;
-  const int tid = threadIdx.x;
-  double acc = 0.0;
-  if (tid < PH * RR) {
-    const int p = tid % RR, ph = tid / RR, ra = p / R, rb = p % R;
-    for (int i = ph; i < s; i += PH) acc += w[(size_t)i * R + ra] * w[(size_t)i * R + rb];
+  constexpr int RR = R * R;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  if constexpr (R <= 4) {
+    double acc[RR];
+#pragma unroll
+    for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+    for (int i = tid; i < s; i += FT) {
+      double x[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[c] = w[(size_t)i * R + c];
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) acc[a * R + b] += x[a] * x[b];
+    }
+#pragma unroll
+    for (int p = 0; p < RR; ++p) {
+      const double v = wave_sum(acc[p]);
+      if (lane == 0) red[wv * RR + p] = v;
+    }
+    __syncthreads();
+    if (tid < RR) {
+      double t = 0.0;
+      for (int q = 0; q < FT / 64; ++q) t += red[q * RR + tid];
+      G[tid] = t;
+    }
+    __syncthreads();
+  } else {
+    constexpr int PH = FT / RR;
+    double acc = 0.0;
+    if (tid < PH * RR) {
+      const int p = tid % RR, ph = tid / RR, ra = p / R, rb = p % R;
+      for (int i = ph; i < s; i += PH) acc += w[(size_t)i * R + ra] * w[(size_t)i * R + rb];
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < RR) {
+      double t = 0.0;
+      for (int ph = 0; ph < PH; ++ph) t += red[ph * RR + tid];
+      G[tid] = t;
+    }
+    __syncthreads();
   }
-  red[tid] = acc;
-  __syncthreads();
-  if (tid < RR) {
-    double t = 0.0;
-    for (int ph = 0; ph < PH; ++ph) t += red[ph * RR + tid];
-    G[tid] = t;
-  }
-  __syncthreads();
 }
 
 // One workgroup per space: CholQR2 of the remainder w, then append q to Q and
@@ -241,10 +285,11 @@ void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const Wh
     const int nsplit = whiten_splits(m);
     const int cps = ceil_div(m, nsplit);
     for (int pass = 0; pass < 2; ++pass) {
-      WH_DISPATCH(r, hipLaunchKernelGGL((qtw_kernel<RR_>), dim3(ceil_div(m, JB), 2), dim3(WT), 0, st, a, b, s, m, pass));
+      WH_DISPATCH(r, hipLaunchKernelGGL((qtw_kernel<RR_>), dim3(ceil_div(m, jb_of<RR_>()), 2), dim3(WT), 0, st, a, b, s,
+                                        m, pass));
       check_launch("whiten_qtw");
-      WH_DISPATCH(r, hipLaunchKernelGGL((qc_part_kernel<RR_>), dim3(ceil_div(s, WT), nsplit, 2), dim3(WT), 0, st, a, b,
-                                        s, m, pass, cps));
+      WH_DISPATCH(r, hipLaunchKernelGGL((qc_part_kernel<RR_>), dim3(ceil_div(s, WT), nsplit, 2), dim3(WT),
+                                        sizeof(double) * (size_t)cps * RR_, st, a, b, s, m, pass, cps));
       check_launch("whiten_qc");
       hipLaunchKernelGGL(wsub_kernel, dim3(std::min(1024, ceil_div((int64_t)s * r, 256)), 2), dim3(256), 0, st, a, b,
                          s, r, nsplit);
