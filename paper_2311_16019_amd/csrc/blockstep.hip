@@ -158,8 +158,16 @@ __global__ void __launch_bounds__(256) reduce_post_kernel(SpaceStep<T> s0, Space
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   for (int i = wv; i < nvals; i += 4) {
     const double* p = sp.part + (size_t)i * sp.nwg;
+    // up to 16 partials per lane (nwg <= 1024): issue all loads, then add in order
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int w = lane + 64 * q;
+      v[q] = (w < sp.nwg) ? p[w] : 0.0;
+    }
     double s = 0.0;
-    for (int w = lane; w < sp.nwg; w += 64) s += p[w];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += v[q];
     s = wave_sum(s);
     if (lane == 0) out[i] = s;
   }

@@ -98,15 +98,16 @@ class Profiler {
     for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : pool_) (void)hipEventDestroy(e);
   }
-  void begin(int fam) {
+  void begin(int fam, hipStream_t s = nullptr) {
     if (!on_) return;
     cur_ = {get(), nullptr, fam};
-    SKR_HIP(hipEventRecord(cur_.a, st_));
+    cur_st_ = s ? s : st_;
+    SKR_HIP(hipEventRecord(cur_.a, cur_st_));
   }
   void end() {
     if (!on_) return;
     cur_.b = get();
-    SKR_HIP(hipEventRecord(cur_.b, st_));
+    SKR_HIP(hipEventRecord(cur_.b, cur_st_));
     pending_.push_back(cur_);
   }
   // call after the stream has been synchronised
@@ -131,7 +132,7 @@ class Profiler {
     return e;
   }
   bool on_;
-  hipStream_t st_;
+  hipStream_t st_, cur_st_ = nullptr;
   Pair cur_{};
   std::vector<Pair> pending_;
   std::vector<hipEvent_t> pool_;
@@ -159,6 +160,10 @@ class Solver {
  public:
   Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
       : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
+    SKR_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+    SKR_HIP(hipEventCreateWithFlags(&ev_block_, hipEventDisableTiming));
+    SKR_HIP(hipEventCreateWithFlags(&ev_sketch_, hipEventDisableTiming));
+    SKR_HIP(hipEventCreateWithFlags(&ev_aux_done_, hipEventDisableTiming));
     SKR_REQUIRE(r >= 1 && r <= RMAX, "r must be in [1, 16]");
     SKR_REQUIRE(p.k >= 1, "k must be >= 1");
     SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
@@ -184,6 +189,23 @@ class Solver {
     lds_limit_ = std::max<size_t>(65536, prop.sharedMemPerBlock);
     setup(sp_[0], A, tu);
     setup(sp_[1], B, tv);
+  }
+
+  ~Solver() {
+    if (aux_) (void)hipStreamSynchronize(aux_);
+    if (ev_block_) (void)hipEventDestroy(ev_block_);
+    if (ev_sketch_) (void)hipEventDestroy(ev_sketch_);
+    if (ev_aux_done_) (void)hipEventDestroy(ev_aux_done_);
+    if (aux_) (void)hipStreamDestroy(aux_);
+  }
+  Solver(const Solver&) = delete;
+  Solver& operator=(const Solver&) = delete;
+
+  // The sketch and the sketched QR update of step d run on the auxiliary stream; the
+  // solve's stream waits for them before anything reads T, Q or the breakdown flags.
+  void join_aux() {
+    SKR_HIP(hipEventRecord(ev_aux_done_, aux_));
+    SKR_HIP(hipStreamWaitEvent(st_, ev_aux_done_, 0));
   }
 
   skr_result_s* run(const double* C1, const double* C2) {
@@ -214,6 +236,7 @@ class Solver {
     for (int d = 1; d <= p_.maxit; ++d) {
       block_step(d);
       if (d % p_.p == 0 || d == p_.maxit) {
+        join_aux();
         SKR_HIP(hipMemcpyAsync(&hb[0], sp_[0].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
         SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
         SKR_HIP(hipEventRecord(e1, st_));
@@ -353,8 +376,8 @@ class Solver {
     const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
     for (int i = 0; i < 2; ++i)
       launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
-    sketch(1);
-    whiten(0, 0);
+    sketch(1, st_);
+    whiten(0, 0, st_);
     F11_.alloc((size_t)r_ * r_);
     hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p, sp_[1].Tm.p,
                        ld_, sp_[1].ell.p, F11_.p);
@@ -368,16 +391,16 @@ class Solver {
     return z ^ (z >> 31);
   }
 
-  void sketch(int j) {
+  void sketch(int j, hipStream_t s) {
     SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].w.p, sp_[0].n, sp_[0].nchunk};
     SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].w.p, sp_[1].n, sp_[1].nchunk};
-    launch_sketch<T>(r_, (int)s_, p_.zeta, k0, k1, lds_limit_, st_);
+    launch_sketch<T>(r_, (int)s_, p_.zeta, k0, k1, lds_limit_, s);
   }
 
-  void whiten(int d, int step) {
+  void whiten(int d, int step, hipStream_t s) {
     WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].w.p, sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p, sp_[0].broken.p, ld_};
     WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].w.p, sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p, sp_[1].broken.p, ld_};
-    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, st_);
+    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s);
   }
 
   void block_step(int d) {
@@ -422,14 +445,23 @@ class Solver {
       prof_.end();
     }
     for (int q = 0; q < 2; ++q) a[q].Unew = sp_[q].slot(d + 1);
+    if (!sp_[0].stored) {
+      // ring buffer: slot(d+1) held U_{d+1-nslots}; its sketch (issued earlier on the
+      // auxiliary stream) must be complete before the slot is overwritten
+      SKR_HIP(hipStreamWaitEvent(st_, ev_sketch_, 0));
+    }
     prof_.begin(KF_NORMALIZE);
     launch_normalize<T>(r_, a[0], a[1], st_);
     prof_.end();
-    prof_.begin(KF_SKETCH);
-    sketch(d + 1);
+    // U_{d+1} is final: sketch it and update Q, T concurrently with the next block step
+    SKR_HIP(hipEventRecord(ev_block_, st_));
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
+    prof_.begin(KF_SKETCH, aux_);
+    sketch(d + 1, aux_);
     prof_.end();
-    prof_.begin(KF_WHITEN);
-    whiten(d, d);
+    SKR_HIP(hipEventRecord(ev_sketch_, aux_));
+    prof_.begin(KF_WHITEN, aux_);
+    whiten(d, d, aux_);
     prof_.end();
   }
 
@@ -516,6 +548,8 @@ class Solver {
   size_t lds_limit_ = 65536;
   Space<T> sp_[2];
   Profiler prof_;
+  hipStream_t aux_ = nullptr;
+  hipEvent_t ev_block_ = nullptr, ev_sketch_ = nullptr, ev_aux_done_ = nullptr;
   DBuf<double> F11_;
   std::vector<double> rhs_block_host_;
 };
