@@ -487,6 +487,9 @@ constexpr int SK_WG = 1024;
 
 // One workgroup per (chunk of rows, copy t): scatter-add signed rows into an LDS copy of
 // the t-th band of the sketch (b x rc doubles, columns [c0, c0+rc)), then write it out.
+// The LDS copy is column-major (acc[c * b + bucket]) so that the 64 random buckets of a
+// wavefront's atomics spread over all LDS banks rather than over the few banks that one
+// column of a row-major copy maps to.
 template <typename T, int R>
 __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, SketchSpace<T> a1, int s, int zeta,
                                                         int c0, int rc) {
@@ -511,13 +514,13 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
     load_block_row<T, R>(sp.U, row, x);
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      if (c >= c0 && c < c0 + rc) atomicAdd(&acc[bucket * rc + (c - c0)], sg * x[c]);
+      if (c >= c0 && c < c0 + rc) atomicAdd(&acc[(c - c0) * b + bucket], sg * x[c]);
   }
   __syncthreads();
   double* out = sp.part + ((size_t)chunk * s + (size_t)t * b) * R;
   for (int i = threadIdx.x; i < b * rc; i += SK_WG) {
     const int bk = i / rc, c = i % rc;
-    out[(size_t)bk * R + c0 + c] = acc[i];
+    out[(size_t)bk * R + c0 + c] = acc[c * b + bk];
   }
 }
 

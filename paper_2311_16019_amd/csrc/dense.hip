@@ -1,5 +1,5 @@
-// FP64 dense kernels for the projected problems: tiled GEMM, blocked LU with partial
-// pivoting, triangular solves and the inverse built from them.
+// FP64 dense kernels for the projected problems: tiled GEMM, triangular solves and
+// elementwise helpers (inverses and dense solves are in gauss_jordan.hip).
 #include <algorithm>
 #include <cmath>
 
@@ -151,192 +151,11 @@ bool run_gemm_splitk(int m, int n, int k, LA la, LB lb, double alpha, double bet
   return true;
 }
 
-// ----------------------------------------------------------------------------- LU
-constexpr int NB = 32;     // LU / TRSM block size
-constexpr int PT = 512;    // panel threads
-
-constexpr int PANEL_LDS_DOUBLES = 16384;  // 128 KB: panels up to rows * nb <= 16384 live in LDS
-constexpr int MAXSWAP = 2 * NB;
-
-// Factor columns [j0, j0+nb) of the n x n matrix A over rows [j0, n) with partial pivoting.
-// The panel is staged in LDS when it fits (otherwise it is factored in place in global
-// memory).  Besides ipiv, the kernel writes the net row permutation of the panel's
-// interchanges as at most 2 nb (destination, source) pairs for the gather in laswp_kernel.
-__global__ void __launch_bounds__(PT) panel_kernel(int n, double* A, int lda, int j0, int nb, int* ipiv, int* info,
-                                                   int* swaps) {
-  extern __shared__ double P[];  // rows x nb, column-major with ld = rows (when staged)
-  __shared__ double wval[PT / 64];
-  __shared__ int widx[PT / 64];
-  __shared__ int piv;
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  const int rows = n - j0;
-  const bool staged = (size_t)rows * nb <= PANEL_LDS_DOUBLES;
-  double* base = staged ? P : A + j0 + (size_t)j0 * lda;
-  const int ld = staged ? rows : lda;
-  if (staged) {
-    for (int e = tid; e < rows * nb; e += PT) {
-      const int i = e % rows, c = e / rows;
-      P[e] = A[(j0 + i) + (size_t)(j0 + c) * lda];
-    }
-    __syncthreads();
-  }
-  for (int c = 0; c < nb; ++c) {  // local column c = global column j0 + c
-    double best = -1.0;
-    int bi = rows;
-    for (int i = c + tid; i < rows; i += PT) {
-      const double v = fabs(base[i + (size_t)c * ld]);
-      if (v > best) { best = v; bi = i; }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if (lane == 0) { wval[wv] = best; widx[wv] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double b = -1.0;
-      int ib = rows;
-      for (int w = 0; w < PT / 64; ++w)
-        if (wval[w] > b || (wval[w] == b && widx[w] < ib)) { b = wval[w]; ib = widx[w]; }
-      if (ib >= rows) ib = c;
-      piv = ib;
-      ipiv[j0 + c] = j0 + ib;
-      if (!(b > 0.0) && *info == 0) *info = j0 + c + 1;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != c)
-      for (int cc = tid; cc < nb; cc += PT) {
-        const double t = base[c + (size_t)cc * ld];
-        base[c + (size_t)cc * ld] = base[p + (size_t)cc * ld];
-        base[p + (size_t)cc * ld] = t;
-      }
-    __syncthreads();
-    const double pv = base[c + (size_t)c * ld];
-    const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-    __shared__ double prow[NB];
-    if (tid < nb) prow[tid] = base[c + (size_t)tid * ld];
-    __syncthreads();
-    const int rem = rows - c - 1;
-    for (int i = c + 1 + tid; i < rows; i += PT) {
-      // the row's panel entries in registers: independent loads, then the update
-      double x[NB];
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) x[cc] = (cc > c && cc < nb) ? base[i + (size_t)cc * ld] : 0.0;
-      const double xc = base[i + (size_t)c * ld];
-      const double l = (pv != 0.0) ? xc * inv : xc;
-      base[i + (size_t)c * ld] = l;
-      if (pv != 0.0) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc)
-          if (cc > c && cc < nb) base[i + (size_t)cc * ld] = x[cc] - l * prow[cc];
-      }
-    }
-    (void)rem;
-    __syncthreads();
-  }
-  if (staged) {
-    for (int e = tid; e < rows * nb; e += PT) {
-      const int i = e % rows, c = e / rows;
-      A[(j0 + i) + (size_t)(j0 + c) * lda] = P[e];
-    }
-  }
-  // Net permutation of the touched rows, tracked by the first wavefront: lane t holds one
-  // touched row (row_t) and the original row now stored there (src_t); each interchange
-  // finds its two lanes with a ballot and swaps their src values with shuffles.
-  if (tid < 64) {
-    int row_t = -1, src_t = -1, used = 0;
-    for (int c = 0; c < nb; ++c) {
-      const int r1 = j0 + c, r2 = ipiv[j0 + c];
-      if (r1 == r2) continue;
-      int l1 = -1, l2 = -1;
-      for (int pass = 0; pass < 2; ++pass) {
-        const int rr = pass ? r2 : r1;
-        const unsigned long long hit = __ballot(row_t == rr);
-        int ln = hit ? __ffsll((long long)hit) - 1 : used;
-        if (!hit) {  // first time this row is touched: claim the next lane
-          if (lane == ln) { row_t = rr; src_t = rr; }
-          ++used;
-        }
-        if (pass) l2 = ln; else l1 = ln;
-      }
-      const int v1 = __shfl(src_t, l1, 64), v2 = __shfl(src_t, l2, 64);
-      if (lane == l1) src_t = v2;
-      if (lane == l2) src_t = v1;
-    }
-    const bool moved = (row_t >= 0) && (src_t != row_t);
-    const unsigned long long mv = __ballot(moved);
-    const int pos = __popcll(mv & ((1ull << lane) - 1ull));
-    if (moved) {
-      swaps[1 + 2 * pos] = row_t;
-      swaps[2 + 2 * pos] = src_t;
-    }
-    if (lane == 0) swaps[0] = __popcll(mv);
-  }
-}
-
-// Apply the panel's row permutation to the columns outside [j0, j0+nb) as a gather.
-__global__ void __launch_bounds__(256) laswp_kernel(int n, double* A, int lda, int j0, int nb, const int* swaps) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ncols = n - nb;
-  if (t >= ncols) return;
-  const int cc = t < j0 ? t : t + nb;
-  const int m = swaps[0];
-  double v[MAXSWAP];
-  double* col = A + (size_t)cc * lda;
-#pragma unroll
-  for (int q = 0; q < MAXSWAP; ++q)
-    if (q < m) v[q] = col[swaps[2 + 2 * q]];
-#pragma unroll
-  for (int q = 0; q < MAXSWAP; ++q)
-    if (q < m) col[swaps[1 + 2 * q]] = v[q];
-}
-
-// Diagonal-block triangular solves.  Each workgroup inverts the nb x nb triangular block in
-// LDS (one column of the inverse per thread), then every thread multiplies its column (or
-// row) of B by the inverse: independent fused multiply-adds instead of a dependent
-// substitution chain.
-
-// B[0:nb, :] <- L^{-1} B, L unit lower triangular; one thread per column of B.
-__global__ void trsm_lln_diag_kernel(int nb, const double* L, int ldl, double* B, int ldb, int ncols) {
-  __shared__ double Ls[NB][NB + 1], Li[NB][NB + 1];
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, j = e / NB;
-    Ls[i][j] = (i < nb && j < nb && i > j) ? L[i + (size_t)j * ldl] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < NB) {  // column j of L^{-1} (forward substitution on e_j), in registers
-    const int j = threadIdx.x;
-    double col[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int l = 0; l < i; ++l) v -= Ls[i][l] * col[l];
-      col[i] = (i >= j) ? v : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Li[i][j] = col[i];
-  }
-  __syncthreads();
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  double x[NB];
-  double* b = B + (size_t)col * ldb;
-#pragma unroll
-  for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? b[i] : 0.0;
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    if (i < nb) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l <= i; ++l) s += Li[i][l] * x[l];
-      b[i] = s;
-    }
-  }
-}
+// ----------------------------------------------------------------------- triangular
+// Triangular solves by NB x NB diagonal blocks: each diagonal block is inverted once into
+// LDS (one thread per column, in registers), then applied as a small dense product;
+// the off-diagonal blocks are GEMM updates.
+constexpr int NB = 32;
 
 // B[0:nb, :] <- U^{-1} B, U upper triangular (non-unit); one thread per column of B.
 __global__ void trsm_lun_diag_kernel(int nb, const double* U, int ldu, double* B, int ldb, int ncols) {
@@ -412,55 +231,6 @@ __global__ void trsm_run_diag_kernel(int nb, const double* T, int ldt, double* B
       for (int l = 0; l <= c; ++l) s += x[l] * Ti[l][c];
       B[row + (size_t)c * ldb] = s;
     }
-  }
-}
-
-__global__ void logdet_kernel(int n, const double* A, int lda, double* out) {
-  __shared__ double red[16];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += log(fabs(A[i + (size_t)i * lda]));
-  s = wave_sum(s);
-  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)blockDim.x / 64; ++w) t += red[w];
-    *out = t;
-  }
-}
-
-// perm[i] = row of the identity that ends up in row i after the interchanges.  The
-// sequential interchanges run on one thread over a copy in LDS (n <= PERM_LDS).
-constexpr int PERM_LDS = 32768;
-__global__ void perm_kernel(int n, const int* ipiv, int* perm) {
-  __shared__ int pl[PERM_LDS];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) pl[i] = i;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int c = 0; c < n; ++c) {
-      const int p = ipiv[c];
-      if (p != c) { const int t = pl[c]; pl[c] = pl[p]; pl[p] = t; }
-    }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = pl[i];
-}
-
-// X = P I:  X(i, j) = [perm[i] == j]
-__global__ void permuted_identity_kernel(int n, const int* perm, double* X, int ldx) {
-  const size_t total = (size_t)n * n;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    X[i + (size_t)j * ldx] = (perm[i] == j) ? 1.0 : 0.0;
-  }
-}
-
-__global__ void apply_pivots_kernel(int n, int nrhs, const int* ipiv, double* B, int ldb) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= nrhs) return;
-  double* b = B + (size_t)col * ldb;
-  for (int c = 0; c < n; ++c) {
-    const int p = ipiv[c];
-    if (p != c) { const double t = b[c]; b[c] = b[p]; b[p] = t; }
   }
 }
 
@@ -553,7 +323,6 @@ int red_grid(size_t total) { return (int)std::max<size_t>(1, std::min<size_t>(RE
 }  // namespace
 
 int scratch_doubles() { return 3 * RED_MAXG; }
-int ipiv_ints(int n) { return 2 * n + 1 + 4 * NB + 8; }
 
 void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc, hipStream_t st) {
@@ -580,78 +349,6 @@ template void basis_gemm<double>(int, int, int, int, double, const double*, cons
                                  hipStream_t);
 template void basis_gemm<float>(int, int, int, int, double, const float*, const double*, int, double, double*, int,
                                 hipStream_t);
-
-void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, hipStream_t st) {
-  SKR_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
-  // the permutation lists of the panels live just past the 2n ints of ipiv
-  int* swaps = ipiv + 2 * (size_t)n;
-  static bool attr_set = false;
-  if (!attr_set) {
-    SKR_HIP(hipFuncSetAttribute((const void*)panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                PANEL_LDS_DOUBLES * (int)sizeof(double)));
-    attr_set = true;
-  }
-  // panel width: the widest power of two (<= NB) whose panel fits in LDS, NB otherwise
-  int pw = NB;
-  while (pw > 4 && (size_t)n * pw > PANEL_LDS_DOUBLES) pw /= 2;
-  if ((size_t)n * pw > PANEL_LDS_DOUBLES) pw = NB;
-  for (int j0 = 0; j0 < n; j0 += pw) {
-    const int nb = std::min(pw, n - j0);
-    const size_t lds = ((size_t)(n - j0) * nb <= PANEL_LDS_DOUBLES) ? (size_t)(n - j0) * nb * sizeof(double) : 0;
-    hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(PT), lds, st, n, A, lda, j0, nb, ipiv, info, swaps);
-    check_launch("lu_panel");
-    if (n - nb > 0) {
-      hipLaunchKernelGGL(laswp_kernel, dim3(ceil_div(n - nb, 256)), dim3(256), 0, st, n, A, lda, j0, nb, swaps);
-      check_launch("laswp");
-    }
-    const int rest = n - j0 - nb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(rest, 256)), dim3(256), 0, st, nb,
-                         A + j0 + (size_t)j0 * lda, lda, A + j0 + (size_t)(j0 + nb) * lda, lda, rest);
-      check_launch("lu_trsm");
-      gemm(false, false, rest, rest, nb, -1.0, A + (j0 + nb) + (size_t)j0 * lda, lda, A + j0 + (size_t)(j0 + nb) * lda,
-           lda, 1.0, A + (j0 + nb) + (size_t)(j0 + nb) * lda, lda, st);
-    }
-  }
-  if (logabsdet) {
-    hipLaunchKernelGGL(logdet_kernel, dim3(1), dim3(1024), 0, st, n, A, lda, logabsdet);
-    check_launch("logdet");
-  }
-}
-
-void trsm_left_lower_unit(int n, int nrhs, const double* L, int ldl, double* B, int ldb, hipStream_t st) {
-  if (n <= 0 || nrhs <= 0) return;
-  for (int b0 = 0; b0 < n; b0 += NB) {
-    const int nb = std::min(NB, n - b0);
-    hipLaunchKernelGGL(trsm_lln_diag_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, st, nb,
-                       L + b0 + (size_t)b0 * ldl, ldl, B + b0, ldb, nrhs);
-    check_launch("trsm_lln");
-    const int below = n - b0 - nb;
-    if (below > 0)
-      gemm(false, false, below, nrhs, nb, -1.0, L + (b0 + nb) + (size_t)b0 * ldl, ldl, B + b0, ldb, 1.0, B + b0 + nb,
-           ldb, st);
-  }
-}
-
-void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st) {
-  // the permutation vector is kept just past the pivots (the caller's ipiv holds 2n ints)
-  int* perm = const_cast<int*>(ipiv) + n;
-  SKR_REQUIRE(n <= PERM_LDS, "matrix too large for the inverse");
-  hipLaunchKernelGGL(perm_kernel, dim3(1), dim3(1024), 0, st, n, ipiv, perm);
-  check_launch("perm");
-  hipLaunchKernelGGL(permuted_identity_kernel, dim3(std::min(8192, ceil_div((int64_t)n * n, 256))), dim3(256), 0, st,
-                     n, perm, X, ldx);
-  check_launch("permuted_identity");
-  trsm_left_lower_unit(n, n, LU, lda, X, ldx, st);
-  trsm_left_upper(n, n, LU, lda, X, ldx, st);
-}
-
-void getrs(int n, int nrhs, const double* LU, int lda, const int* ipiv, double* B, int ldb, hipStream_t st) {
-  hipLaunchKernelGGL(apply_pivots_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, st, n, nrhs, ipiv, B, ldb);
-  check_launch("apply_pivots");
-  trsm_left_lower_unit(n, nrhs, LU, lda, B, ldb, st);
-  trsm_left_upper(n, nrhs, LU, lda, B, ldb, st);
-}
 
 void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st) {
   if (n <= 0 || nrhs <= 0) return;

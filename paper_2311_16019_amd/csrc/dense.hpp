@@ -1,5 +1,5 @@
 // FP64 dense linear algebra on the device for the small projected problems (sizes up to a
-// few thousand): tiled GEMM, blocked LU with partial pivoting, triangular solves, inverse.
+// few thousand): tiled GEMM, Gauss-Jordan inverse and solve, triangular solves.
 // All matrices are column-major with explicit leading dimensions.
 #pragma once
 
@@ -19,20 +19,19 @@ template <typename T>
 void basis_gemm(int n, int r, int nb, int l, double alpha, const T* U, const double* W, int ldw, double beta,
                 double* X, int ldx, hipStream_t st);
 
-// In-place LU with partial pivoting of the n x n matrix A: P A = L U (unit L).  ipiv (device,
-// room for 2n + 1 + 4*32 ints; the tail is workspace) receives 0-based pivot rows; info (device int) is set to 1 + the first zero
-// pivot column if the matrix is exactly singular.  logabsdet (device double, may be null)
-// receives sum log|U_ii|.
-void getrf(int n, double* A, int lda, int* ipiv, int* info, double* logabsdet, hipStream_t st);
+// Blocked Gauss-Jordan elimination with partial pivoting of the first n columns of the
+// n x ncols matrix S (column-major, leading dimension lds), in place and without moving
+// rows.  iws holds gj_ints(n) ints (pivot rows, their inverse, flags) and dws gj_doubles(n)
+// doubles.  info (device int) is set to 1 + the first column without a nonzero pivot;
+// logabsdet (device double, may be null) receives log|det A|.  The results are read with
+// gj_inverse (A^{-1}) and gj_solution (A^{-1} B for the columns n .. ncols-1 of S).
+void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
+                  hipStream_t st);
+void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st);
+void gj_solution(int n, int nrhs, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st);
+int gj_ints(int n);
+int gj_doubles(int n);
 
-// X = A^{-1} from the LU factors of getrf.  X is n x n with leading dimension ldx; ipiv is
-// the array passed to getrf (its workspace tail is reused).
-void getri(int n, const double* LU, int lda, const int* ipiv, double* X, int ldx, hipStream_t st);
-
-// Solve A X = B in place from the LU factors of getrf (B n x nrhs).
-void getrs(int n, int nrhs, const double* LU, int lda, const int* ipiv, double* B, int ldb, hipStream_t st);
-// Solve L X = B in place, L unit lower triangular n x n.
-void trsm_left_lower_unit(int n, int nrhs, const double* L, int ldl, double* B, int ldb, hipStream_t st);
 // Solve T X = B in place (B <- T^{-1} B), T upper triangular n x n, B n x nrhs.
 void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st);
 // Solve X T = B in place (B <- B T^{-1}), T upper triangular n x n, B m x n.
@@ -50,7 +49,6 @@ void newton_combine(int m, int n, const double* mu_dev, const double* X, int ldx
 void fro2(int m, int n, const double* A, int lda, double* out, double* scratch, hipStream_t st);
 
 int scratch_doubles();  // size of the `scratch` buffer the reductions need
-int ipiv_ints(int n);   // size of the ipiv array getrf/getri need for an n x n matrix
 
 }  // namespace dense
 }  // namespace skr

@@ -1,0 +1,430 @@
+// Blocked Gauss-Jordan elimination with partial pivoting (FP64) for the inverses of the
+// projected Newton iteration and for small dense solves.
+//
+// Rows are never interchanged in memory.  The pivot of column k is the row piv[k], chosen
+// by largest modulus among the rows not yet used as pivots, and the eliminated column k
+// stores column piv[k] of the accumulated elimination matrix E (E A = Pi, Pi(:, k) =
+// e_{piv[k]}).  Afterwards A^{-1}(i, j) = S(piv[i], pos[j]) with pos the inverse of piv,
+// and for extra columns B of S the solution of A X = B is X(i, c) = S(piv[i], n + c).
+//
+// Blocking: columns are eliminated in panels of NB.  Panel b's combined transformation E_b
+// differs from the identity only in the panel's pivot rows P_b, and the panel's columns
+// K_b hold E_b(:, P_b) once the panel is eliminated, so every other column j receives it as
+// one rank-NB update
+//     S(:, j) <- S(:, j) + S(:, K_b) a - sum_t a_t e_{P_b[t]},   a = S(P_b, j).
+// Launch b runs one workgroup that applies E_{b-1} to the columns of panel b and then
+// eliminates panel b in registers (one barrier per column), and many workgroups that apply
+// E_{b-1} to all remaining columns: n / NB + 1 launches for the whole elimination.  The
+// panel workgroup has one wavefront per SIMD: the per-column pivot search and broadcast
+// are latency chains, and more wavefronts would only time-share the SIMDs on them.
+#include <climits>
+#include <cmath>
+
+#include "dense.hpp"
+
+namespace skr {
+namespace dense {
+namespace {
+
+constexpr int GJ_T = 256;         // threads per workgroup: one wavefront per SIMD
+constexpr int GJ_W = GJ_T / 64;   // wavefronts per workgroup
+constexpr int GJ_CW = 4;          // columns per strip of an update workgroup
+constexpr int GJ_MAXUPD = 511;    // update workgroups per launch
+
+struct GjArgs {
+  int n, ncols, ld, b, nblk, nupd;
+  int wide;           // columns are 16-byte aligned (even ld, aligned S)
+  double* S;
+  int* piv;
+  int* pos;
+  int* used;
+  int* info;
+  double* pivabs;     // |pivot| of every column (summed as logs by the final launch)
+  double* logabsdet;  // sum over all panels (may be null)
+};
+
+__global__ void gj_init_kernel(int n, int* used, int* info) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) used[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+}
+
+// Pivot search key: the IEEE bits of |v| (monotone for nonnegative doubles) with the low
+// 24 bits replaced by 2^24 - 1 - row, so that the largest key is the largest modulus and,
+// among moduli equal to 28 mantissa bits, the smallest row.  Rows that may not pivot get
+// key 0; every eligible row has a key >= 1 even when its entry is zero.
+__device__ inline uint64_t pivot_key(double av, int row) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(av);
+  return (bits & ~0xFFFFFFull) | (uint64_t)(0xFFFFFF - row);
+}
+__device__ inline int key_row(uint64_t key) { return 0xFFFFFF - (int)(key & 0xFFFFFFull); }
+
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Maximum over the wavefront, returned uniformly: butterflies within each row of 16 lanes
+// (DPP quad permutations and row rotations), then the four row maxima via readlane.
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+  uint64_t o;
+  o = dpp_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = o > v ? o : v;
+  o = dpp_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = o > v ? o : v;
+  o = dpp_u64<0x124>(v);  // row_ror:4
+  v = o > v ? o : v;
+  o = dpp_u64<0x128>(v);  // row_ror:8
+  v = o > v ? o : v;
+  uint64_t m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * r);
+    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    m = x > m ? x : m;
+  }
+  return m;
+}
+
+// One row set per thread: row(q) = threadIdx.x + GJ_T q.
+template <int RPT>
+__device__ inline int row_of(int q) { return threadIdx.x + GJ_T * q; }
+
+// Panel workgroup of launch b: apply E_{b-1} to the columns K_b, then eliminate K_b.
+template <int RPT, int NB>
+__device__ void panel_workgroup(const GjArgs& g, double* sl) {
+  __shared__ int pl[NB];
+  __shared__ int pivl[NB];
+  __shared__ double amat[NB][NB];
+  __shared__ uint64_t ckey[2][GJ_W];
+  __shared__ double crow[2][GJ_W][NB];
+  __shared__ double red[GJ_W];
+  const int tid = threadIdx.x, wv = tid / 64;
+  if (g.b == g.nblk) {  // final launch: log|det A| = sum of log|pivot|, in a fixed order
+    if (g.logabsdet) {
+      double l = 0.0;
+      for (int k = tid; k < g.n; k += GJ_T) l += (g.pivabs[k] > 0.0) ? log(g.pivabs[k]) : 0.0;
+      l = wave_sum(l);
+      if (tid % 64 == 0) red[wv] = l;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < GJ_W; ++w) t += red[w];
+        *g.logabsdet = t;
+      }
+    }
+    return;
+  }
+  const int k0 = g.b * NB, nbc = min(NB, g.n - k0);
+  double x[RPT][NB];
+  bool elig[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int row = row_of<RPT>(q);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[q][c] = (row < g.n && c < nbc) ? g.S[row + (size_t)(k0 + c) * g.ld] : 0.0;
+    elig[q] = (row < g.n) && (g.used[row] == 0);
+  }
+  if (g.b > 0) {  // the previous panel (always full) applied to this panel's columns
+    // Its columns S(:, K_{b-1}) are staged in LDS by direct global-to-LDS loads (no
+    // registers, all in flight at once) into sl[t * ROWS + row]: one instruction moves 128
+    // rows of a column (16 bytes per lane) when the columns are 16-byte aligned, else 32
+    // rows (4 bytes per lane).  A lane whose pair of rows
+    // straddles row n reads the first entry of the next column, which exists (panel b-1
+    // is not the last column), and lands in an unused LDS row.
+    const int kp0 = k0 - NB;
+    constexpr int ROWS = GJ_T * RPT;
+    {
+      const int lane = tid % 64;
+      const bool wide = g.wide != 0;
+      const int rows_per = wide ? 128 : 32, nch = (g.n + rows_per - 1) / rows_per;
+      for (int e = wv; e < NB * nch; e += GJ_W) {
+        const int t = e / nch, j = e % nch;
+        const double* col = g.S + (size_t)(kp0 + t) * g.ld;
+        auto* dst = (__attribute__((address_space(3))) void*)(sl + t * ROWS + rows_per * j);
+        if (wide) {
+          if (rows_per * j + 2 * lane < g.n) __builtin_amdgcn_global_load_lds(col + rows_per * j + 2 * lane, dst, 16, 0, 0);
+        } else {
+          const char* cb = reinterpret_cast<const char*>(col) + 256 * j + 4 * lane;
+          if (256 * j + 4 * lane < 8 * g.n) __builtin_amdgcn_global_load_lds(cb, dst, 4, 0, 0);
+        }
+      }
+    }
+    if (tid < NB) pl[tid] = g.piv[kp0 + tid];
+    __syncthreads();
+    // amat(t, :) = S(P_{b-1}[t], K_b): the pivot rows' entries of this panel, taken from the
+    // registers of the threads that own those rows
+    int tp[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = row_of<RPT>(q);
+      tp[q] = -1;
+      for (int t = 0; t < NB; ++t)
+        if (pl[t] == row) tp[q] = t;
+      if (tp[q] >= 0)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) amat[tp[q]][c] = x[q][c];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int t = 0; t < NB; ++t) {
+      double sv[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) sv[q] = sl[t * ROWS + row_of<RPT>(q)];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double a = amat[t][c];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) x[q][c] += sv[q] * a;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (tp[q] >= 0)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[q][c] -= amat[tp[q]][c];
+  }
+  // Eliminate the panel's columns: per column one pivot search (keys reduced within each
+  // wavefront, then over the GJ_W candidates published in LDS) and one barrier; the LDS
+  // records are double-buffered so the next column's writes cannot race this column's reads.
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c >= nbc) continue;  // uniform; keeps the loop fully unrollable
+    const int buf = c & 1;
+    uint64_t key = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const uint64_t kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT>(q)) : 0ull;
+      key = kq > key ? kq : key;
+    }
+    const uint64_t wkey = wave_max_u64(key);  // uniform over the wavefront
+    if (wkey != 0) {
+      const int wr = key_row(wkey), wq = wr / GJ_T;  // wq uniform: scalar branches below
+      if (wr % GJ_T == tid) {
+        ckey[buf][wv] = wkey;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == wq)
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) crow[buf][wv][cc] = x[q][cc];
+      }
+    } else if (tid % 64 == 0) {
+      ckey[buf][wv] = 0;
+    }
+    __syncthreads();
+    uint64_t gk = 0;
+    int gw = 0;
+#pragma unroll
+    for (int w = 0; w < GJ_W; ++w) {
+      const uint64_t kw = ckey[buf][w];
+      if (kw > gk) { gk = kw; gw = w; }
+    }
+    const int gr = key_row(gk);
+    double ps[NB];
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) ps[cc] = crow[buf][gw][cc];
+    const double pv = ps[c];
+    const bool ok = (pv != 0.0) && (gk != 0);
+    const double inv = ok ? 1.0 / pv : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) ps[cc] *= inv;
+    // every row takes the elimination update (no divergent branch); the pivot row's owner
+    // then overwrites it with the scaled pivot row
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double f = x[q][c];
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc)
+        if (cc != c) x[q][cc] -= f * ps[cc];
+      x[q][c] = -f * inv;
+    }
+    if (gr % GJ_T == tid) {
+      const int gq = gr / GJ_T;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (q == gq) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) x[q][cc] = (cc == c) ? inv : ps[cc];
+          elig[q] = false;
+        }
+    }
+    if (tid == 0) {
+      pivl[c] = gr;
+      g.pivabs[k0 + c] = ok ? fabs(pv) : 0.0;
+      if (!ok) atomicCAS(g.info, 0, k0 + c + 1);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int row = row_of<RPT>(q);
+    if (row >= g.n) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nbc) g.S[row + (size_t)(k0 + c) * g.ld] = x[q][c];
+  }
+  __syncthreads();
+  if (tid < nbc) {
+    const int p = pivl[tid];
+    g.piv[k0 + tid] = p;
+    g.pos[p] = k0 + tid;
+    g.used[p] = 1;
+  }
+}
+
+// Update workgroup of launch b >= 1: apply E_{b-1} to its strips of columns outside
+// K_{b-1} and K_b.
+template <int RPT, int NB>
+__device__ void update_workgroup(const GjArgs& g) {
+  __shared__ int pl[NB];
+  __shared__ double am[NB][GJ_CW];
+  const int tid = threadIdx.x;
+  const int kp0 = (g.b - 1) * NB, nbp = min(NB, g.n - kp0);
+  const int kb0 = g.b * NB, kb1 = (g.b < g.nblk) ? min(g.n, kb0 + NB) : kb0;
+  if (tid < nbp) pl[tid] = g.piv[kp0 + tid];
+  __syncthreads();
+  double s[RPT][NB];
+  int tp[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int row = row_of<RPT>(q);
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      s[q][t] = (row < g.n && t < nbp) ? g.S[row + (size_t)(kp0 + t) * g.ld] : 0.0;
+    tp[q] = -1;
+    for (int t = 0; t < nbp; ++t)
+      if (pl[t] == row) tp[q] = t;
+  }
+  auto skip = [&](int j) { return j >= g.ncols || (j >= kp0 && j < kp0 + nbp) || (j >= kb0 && j < kb1); };
+  const int nstrips = (g.ncols + GJ_CW - 1) / GJ_CW;
+  for (int strip = blockIdx.x - 1; strip < nstrips; strip += g.nupd) {
+    const int j0 = strip * GJ_CW;
+    for (int e = tid; e < NB * GJ_CW; e += GJ_T) {
+      const int t = e / GJ_CW, jj = e % GJ_CW, j = j0 + jj;
+      am[t][jj] = (t < nbp && !skip(j)) ? g.S[pl[t] + (size_t)j * g.ld] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < GJ_CW; ++jj) {
+      const int j = j0 + jj;
+      if (skip(j)) continue;
+      double* col = g.S + (size_t)j * g.ld;
+      double acc[RPT], v[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        acc[q] = 0.0;
+        v[q] = (row_of<RPT>(q) < g.n) ? col[row_of<RPT>(q)] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const double a = am[t][jj];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] += s[q][t] * a;
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = row_of<RPT>(q);
+        if (row >= g.n) continue;
+        double w = v[q] + acc[q];
+        if (tp[q] >= 0) w -= am[tp[q]][jj];
+        col[row] = w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int RPT, int NB>
+__global__ void __launch_bounds__(GJ_T) gj_step_kernel(GjArgs g) {
+  extern __shared__ double sl[];  // GJ_T * RPT * NB doubles, panel workgroup only
+  if (blockIdx.x == 0) panel_workgroup<RPT, NB>(g, sl);
+  else if (g.b > 0) update_workgroup<RPT, NB>(g);
+}
+
+__global__ void gj_gather_inverse_kernel(int n, const double* S, int lds, const int* piv, const int* pos, double* X,
+                                         int ldx) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    X[i + (size_t)j * ldx] = S[piv[i] + (size_t)pos[j] * lds];
+  }
+}
+
+__global__ void gj_gather_solution_kernel(int n, int nrhs, const double* S, int lds, const int* piv, double* X,
+                                          int ldx) {
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    X[i + (size_t)c * ldx] = S[piv[i] + (size_t)(n + c) * lds];
+  }
+}
+
+template <int RPT, int NB>
+void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
+            hipStream_t st) {
+  GjArgs g{};
+  g.n = n;
+  g.ncols = ncols;
+  g.ld = lds;
+  g.wide = (lds % 2 == 0) && (reinterpret_cast<uintptr_t>(S) % 16 == 0);
+  g.nblk = (n + NB - 1) / NB;
+  g.nupd = std::min(GJ_MAXUPD, (ncols + GJ_CW - 1) / GJ_CW);
+  g.S = S;
+  g.piv = iws;
+  g.pos = iws + n;
+  g.used = iws + 2 * (size_t)n;
+  g.info = info;
+  g.pivabs = dws;
+  g.logabsdet = logabsdet;
+  hipLaunchKernelGGL(gj_init_kernel, dim3(std::max(1, std::min(64, ceil_div(n, 256)))), dim3(256), 0, st, n, g.used,
+                     info);
+  check_launch("gj_init");
+  const int lds_bytes = GJ_T * RPT * NB * (int)sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
+    attr_set = true;
+  }
+  for (int b = 0; b <= g.nblk; ++b) {
+    g.b = b;
+    const int grid = (b == 0) ? 1 : 1 + g.nupd;
+    // only launches with a previous panel stage it; the update workgroups need no LDS
+    hipLaunchKernelGGL((gj_step_kernel<RPT, NB>), dim3(grid), dim3(GJ_T), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
+    check_launch("gj_step");
+  }
+}
+
+}  // namespace
+
+int gj_ints(int n) { return 3 * n; }
+int gj_doubles(int n) { return n + 1; }
+
+void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
+                  hipStream_t st) {
+  SKR_REQUIRE(n >= 1 && ncols >= n && lds >= n, "Gauss-Jordan elimination: bad sizes");
+  SKR_REQUIRE(n <= 64 * GJ_T, "Gauss-Jordan elimination supports n <= 16384");
+  // RPT rows per thread and panel width NB with RPT * NB <= 64 register doubles
+  if (n <= GJ_T) run_gj<1, 32>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 2 * GJ_T) run_gj<2, 32>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 4 * GJ_T) run_gj<4, 16>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 8 * GJ_T) run_gj<8, 8>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 16 * GJ_T) run_gj<16, 4>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 32 * GJ_T) run_gj<32, 2>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else run_gj<64, 1>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+}
+
+void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st) {
+  const int grid = std::max(1, std::min(4096, ceil_div((int64_t)n * n, 256)));
+  hipLaunchKernelGGL(gj_gather_inverse_kernel, dim3(grid), dim3(256), 0, st, n, S, lds, iws, iws + n, X, ldx);
+  check_launch("gj_inverse");
+}
+
+void gj_solution(int n, int nrhs, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st) {
+  const int grid = std::max(1, std::min(4096, ceil_div((int64_t)n * nrhs, 256)));
+  hipLaunchKernelGGL(gj_gather_solution_kernel, dim3(grid), dim3(256), 0, st, n, nrhs, S, lds, iws, X, ldx);
+  check_launch("gj_solution");
+}
+
+}  // namespace dense
+}  // namespace skr

@@ -7,7 +7,7 @@
 //     C_{k+1} = (mu C_k + A_k^{-1} C_k B_k^{-1}/mu)/2,
 // A_k -> sign(M_A), B_k -> sign(M_B^T) and C_k -> 2 Y when both sign limits are the
 // identity (all eigenvalues in the open right half plane, the case of the positive real
-// operators this solver targets).  Every iteration is two LU-based inversions and two GEMMs,
+// operators this solver targets).  Every iteration is two Gauss-Jordan inversions and two GEMMs,
 // which map onto the GPU; the paper solves the same equation with Bartels-Stewart (Sec. 6),
 // whose Schur decompositions do not.  When a limit is not the identity the projected
 // matrix is indefinite (the paper's Example 4.5 shows this can happen) and the solve
@@ -420,8 +420,10 @@ ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st
   mbar_u_.alloc((size_t)(mmax + r) * mmax);
   mbar_v_.alloc((size_t)(mmax + r) * mmax);
   a_.alloc(mm); b_.alloc(mm); ai_.alloc(mm); bi_.alloc(mm); c_.alloc(mm); w1_.alloc(mm); w2_.alloc(mm); lu_.alloc(mm);
-  ipiv_.alloc(dense::ipiv_ints(mmax));
-  ipivb_.alloc(dense::ipiv_ints(mmax));
+  gjw_a_.alloc(dense::gj_ints(mmax));
+  gjw_b_.alloc(dense::gj_ints(mmax));
+  gjd_a_.alloc(dense::gj_doubles(mmax));
+  gjd_b_.alloc(dense::gj_doubles(mmax));
   lub_.alloc(mm);
   info_.alloc(2);
   scal_.alloc(SCAL_N);
@@ -501,9 +503,10 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qre, q, 0.0, Rtre, m, st_);
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qim, q, 0.0, Rtim, m, st_);
   const int n2 = 2 * m;
-  if (!kbuf_.p || kbuf_.n < (size_t)n2 * n2) {
-    kbuf_.alloc((size_t)4 * mmax_ * mmax_);
-    ipiv2_.alloc(dense::ipiv_ints(2 * mmax_));
+  if (!kbuf_.p || kbuf_.n < (size_t)n2 * (n2 + 1)) {
+    kbuf_.alloc((size_t)2 * mmax_ * (2 * mmax_ + 1));
+    gjw2_.alloc(dense::gj_ints(2 * mmax_));
+    gjd2_.alloc(dense::gj_doubles(2 * mmax_));
   }
   for (int j = 0; j < q; ++j) {
     hipLaunchKernelGGL(cplx_rhs_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, q, Rtre, Rtim,
@@ -512,8 +515,10 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
     hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0, st_,
                        m, Al, lal, Tre, Tim, q, j, kbuf_.p);
     check_launch("build_shift");
-    dense::getrf(n2, kbuf_.p, n2, ipiv2_.p, info_.p, nullptr, st_);
-    dense::getrs(n2, 1, kbuf_.p, n2, ipiv2_.p, rhs2, n2, st_);
+    // [K | rhs] eliminated in place; the solution overwrites rhs
+    dense::copy(n2, 1, rhs2, n2, kbuf_.p + (size_t)n2 * n2, n2, st_);
+    dense::gj_eliminate(n2, n2 + 1, kbuf_.p, n2, gjw2_.p, gjd2_.p, info_.p, nullptr, st_);
+    dense::gj_solution(n2, 1, kbuf_.p, n2, gjw2_.p, rhs2, n2, st_);
     hipLaunchKernelGGL(split_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, rhs2, Zre, Zim);
     check_launch("split");
   }
@@ -550,12 +555,12 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     SKR_HIP(hipEventRecord(ev_main_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
     dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
-    dense::getrf(m, lub_.p, m, ipivb_.p, info_.p + 1, s + LDB, aux_);
-    dense::getri(m, lub_.p, m, ipivb_.p, bi_.p, m, aux_);
+    dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
+    dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
     SKR_HIP(hipEventRecord(ev_aux_, aux_));
     dense::copy(m, m, a_.p, m, lu_.p, m, st_);
-    dense::getrf(m, lu_.p, m, ipiv_.p, info_.p, s + LDA, st_);
-    dense::getri(m, lu_.p, m, ipiv_.p, ai_.p, m, st_);
+    dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, s + LDA, st_);
+    dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
     SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
     hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
     check_launch("mu");

@@ -55,12 +55,13 @@ class ProjSolver {
   hipStream_t aux_ = nullptr;  // second stream: the two inversions of a Newton step overlap
   hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr;
   DBuf<double> lub_;
-  DBuf<int> ipivb_;
   DBuf<double> mbar_u_, mbar_v_, a_, b_, ai_, bi_, c_, w1_, w2_, lu_, y1_, y2_;
-  DBuf<int> ipiv_, info_;
+  DBuf<int> gjw_a_, gjw_b_, info_;
+  DBuf<double> gjd_a_, gjd_b_;
   DBuf<double> scal_, scratch_;
   DBuf<double> acapart_, dws_, kbuf_;
-  DBuf<int> ipiv2_;
+  DBuf<int> gjw2_;
+  DBuf<double> gjd2_;
   DBuf<int> acaint_;
 };
 

@@ -165,3 +165,25 @@ def test_full_size_convdiff_fixed_d():
         dist = product_distance(g, o)
         assert dist <= TOL[precision][0], (precision, dist)
         assert history_ratio(g, o) <= TOL[precision][1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_indefinite_operators_take_the_deflated_solve(precision):
+    """A = L + diag(sigma) - 30 I and B = L - 60 I on a 30 x 30 grid: one eigenvalue of A
+    and three of B lie in the left half plane (no eigenvalue of A meets one of -B), so the
+    projected matrices are indefinite and the sign iteration's limits are not the
+    identity.  The GPU must take the spectral deflation and still match the oracle's
+    Bartels-Stewart solution."""
+    import paper_2311_16019_amd as skr
+    from workloads.stencil import with_diag_shift
+    cfg = make_config("reaction2d_500", m=30)
+    n, d = cfg["n"], 30
+    cfg = dict(cfg, sigma=cfg["sigma"] - 30.0, B=with_diag_shift(cfg["B"], np.full(n, -60.0)))
+    prm = dict(k=2, maxit=d, p=d, s=128, seed=cfg["sketch_seed"], tol=0.0)
+    print(f"indefinite reaction m=30 d={d} {precision}", flush=True)
+    g, _ = gpu_solve(cfg, precision=precision, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert g.proj["neg_a"] >= 1 and g.proj["neg_b"] >= 1, g.proj
+    tol_x, tol_h = TOL[precision]
+    assert product_distance(g, o) <= tol_x
+    assert history_ratio(g, o) <= tol_h
