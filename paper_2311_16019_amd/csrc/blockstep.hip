@@ -8,63 +8,11 @@
 #include <climits>
 
 #include "blockstep.hpp"
+#include "small_la.hpp"
 
 namespace skr {
 namespace {
 
-
-// Logical workgroup id such that each XCD (workgroups are dealt round-robin over the 8
-// XCDs by hardware id) owns a contiguous range of logical ids, hence contiguous rows.
-__device__ inline int xcd_logical(int g, int G) {
-  if (G % 8 != 0) return g;
-  return (g % 8) * (G / 8) + g / 8;
-}
-
-// ------------------------------------------------------------------ small FP64 helpers
-// Upper Cholesky factor of a symmetric r x r matrix G (row-major): U^T U = G.
-__device__ bool chol_upper(const double* G, double* U, int r) {
-  for (int i = 0; i < r * r; ++i) U[i] = 0.0;
-  for (int j = 0; j < r; ++j) {
-    double s = G[j * r + j];
-    for (int k = 0; k < j; ++k) s -= U[k * r + j] * U[k * r + j];
-    if (!(s > 0.0)) return false;
-    double d = sqrt(s);
-    U[j * r + j] = d;
-    for (int i = j + 1; i < r; ++i) {
-      double t = G[j * r + i];
-      for (int k = 0; k < j; ++k) t -= U[k * r + j] * U[k * r + i];
-      U[j * r + i] = t / d;
-    }
-  }
-  return true;
-}
-
-// Inverse of an upper triangular r x r matrix (row-major).
-__device__ void inv_upper(const double* U, double* V, int r) {
-  for (int i = 0; i < r * r; ++i) V[i] = 0.0;
-  for (int j = 0; j < r; ++j) {
-    V[j * r + j] = 1.0 / U[j * r + j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s += U[i * r + k] * V[k * r + j];
-      V[i * r + j] = -s / U[i * r + i];
-    }
-  }
-}
-
-__device__ void matmul_small(const double* A, const double* B, double* C, int r) {
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s += A[i * r + k] * B[k * r + j];
-      C[i * r + j] = s;
-    }
-}
-
-__device__ void set_identity(double* A, int r) {
-  for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) A[i * r + j] = (i == j) ? 1.0 : 0.0;
-}
 
 // Breakdown thresholds (not discussed in the paper; the same values as the FP64 oracle).
 constexpr double BREAK_NORM = 1e-12;
@@ -524,14 +472,29 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
   }
 }
 
+// w = (sum over chunks of the partial sketches) P / sqrt(zeta); one thread per sketch row,
+// P (r x r row-major) the block's pending right factor or null for the identity.
 template <typename T>
-__global__ void sketch_reduce_kernel(SketchSpace<T> a0, SketchSpace<T> a1, int s, int r, double scale) {
-  const int total = s * r;
+__global__ void sketch_reduce_kernel(SketchSpace<T> a0, SketchSpace<T> a1, const double* P0, const double* P1, int s,
+                                     int r, double scale) {
   const SketchSpace<T>& sp = blockIdx.y ? a1 : a0;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int ch = 0; ch < sp.nchunk; ++ch) acc += sp.part[(size_t)ch * total + e];
-    sp.w[e] = acc * scale;
+  const double* P = blockIdx.y ? P1 : P0;
+  const size_t total = (size_t)s * r;
+  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < s; row += gridDim.x * blockDim.x) {
+    double acc[RMAX];
+    for (int c = 0; c < r; ++c) {
+      double t = 0.0;
+      for (int ch = 0; ch < sp.nchunk; ++ch) t += sp.part[(size_t)ch * total + (size_t)row * r + c];
+      acc[c] = t;
+    }
+    for (int b = 0; b < r; ++b) {
+      double t = acc[b];
+      if (P) {
+        t = 0.0;
+        for (int c = 0; c < r; ++c) t += acc[c] * P[c * r + b];
+      }
+      sp.w[(size_t)row * r + b] = t * scale;
+    }
   }
 }
 
@@ -604,8 +567,8 @@ void launch_build_sketch_table(uint16_t* tab, int n, int zeta, int b, uint64_t s
 }
 
 template <typename T>
-void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b, size_t lds_limit,
-                   hipStream_t st) {
+void launch_sketch_pending(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b,
+                           const double* Pa, const double* Pb, size_t lds_limit, hipStream_t st) {
   const int bands = s / zeta;
   int rc = (int)std::min<size_t>((size_t)r, lds_limit / (sizeof(double) * (size_t)bands));
   SKR_REQUIRE(rc >= 1, "sketch band does not fit in LDS");
@@ -620,10 +583,15 @@ void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const Sketch
     });
     check_launch("sketch");
   }
-  const int total = s * r;
-  hipLaunchKernelGGL(sketch_reduce_kernel<T>, dim3(std::min(1024, ceil_div(total, 256)), 2), dim3(256), 0, st, a, b,
-                     s, r, 1.0 / sqrt((double)zeta));
+  hipLaunchKernelGGL(sketch_reduce_kernel<T>, dim3(std::min(1024, ceil_div(s, 256)), 2), dim3(256), 0, st, a, b, Pa,
+                     Pb, s, r, 1.0 / sqrt((double)zeta));
   check_launch("sketch_reduce");
+}
+
+template <typename T>
+void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b, size_t lds_limit,
+                   hipStream_t st) {
+  launch_sketch_pending<T>(r, s, zeta, a, b, nullptr, nullptr, lds_limit, st);
 }
 
 #define SKR_INST(T)                                                                                  \
@@ -631,7 +599,9 @@ void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const Sketch
   template void launch_axpy_reduce<T>(int, const SpaceStep<T>&, const SpaceStep<T>&, hipStream_t);  \
   template void launch_gram2<T>(int, const SpaceStep<T>&, const SpaceStep<T>&, hipStream_t);        \
   template void launch_normalize<T>(int, const SpaceStep<T>&, const SpaceStep<T>&, hipStream_t);    \
-  template void launch_sketch<T>(int, int, int, const SketchSpace<T>&, const SketchSpace<T>&, size_t, hipStream_t);
+  template void launch_sketch<T>(int, int, int, const SketchSpace<T>&, const SketchSpace<T>&, size_t, hipStream_t); \
+  template void launch_sketch_pending<T>(int, int, int, const SketchSpace<T>&, const SketchSpace<T>&, const double*, \
+                                         const double*, size_t, hipStream_t);
 SKR_INST(double)
 SKR_INST(float)
 

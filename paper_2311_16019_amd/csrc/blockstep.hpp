@@ -71,5 +71,57 @@ void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const Sketch
                    size_t lds_limit, hipStream_t st);
 
 int sketch_chunks(int n);
+// Sketch with a pending right factor: w = (S U') P / sqrt(zeta), P (r x r row-major, device)
+// or null for the identity.
+template <typename T>
+void launch_sketch_pending(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b,
+                           const double* Pa, const double* Pb, size_t lds_limit, hipStream_t st);
+
+// ---- Two-pass block step (truncated block classical Gram-Schmidt, reorthogonalised through
+// the window Gram matrix, with Cholesky QR twice).  The stored basis block is U'_j with
+// U_j = U'_j P_j for a pending r x r factor P_j kept on the device, so that the second
+// Cholesky factor never needs a pass of its own.
+constexpr int CGS_KMAX = 3;   // window blocks handled by the two-pass step (k <= 3)
+constexpr int CGS_RMAX = 4;   // block sizes handled by the two-pass step (r <= 4)
+
+inline bool cgs_supported(int r, int k) { return r <= CGS_RMAX && k <= CGS_KMAX; }
+
+template <typename T>
+struct CgsPass {
+  CsrView<T> A;               // operator (pass 1)
+  const T* X;                 // U'_d, the SpMM input (pass 1)
+  const double* src;          // pass 1 reads this n x r FP64 block instead of the SpMM (start block)
+  const double* Pd;           // pending factor of X (r x r row-major), null = identity
+  T* Y;                       // U~ (pass 1 output, pass 2 input)
+  T* Unew;                    // U'_{d+1} (pass 2 output)
+  const T* W[CGS_KMAX];       // window blocks U'_{i0} .. U'_d
+  const double* coef;         // pass 2: [R1^{-1} | C_0 .. C_{nw-1}], r x r row-major each
+  double* part;               // per-workgroup partials, value-major
+  int n, nwg;
+};
+
+// Per-space small state of the two-pass step (device pointers, FP64, r x r row-major blocks).
+struct CgsSmall {
+  double* part;               // partials of the pass just run
+  int nwg;
+  double* Pall;               // P_j at Pall + j r^2 (j = 0 .. maxit + 1)
+  double* Gall;               // U'_j^T U'_j at Gall + j r^2
+  double* Xall;               // U'_{j-1-t}^T U'_j at Xall + (j KMAX + t) r^2
+  double* state;              // CgsLayout
+  double* H;                  // Hessenberg matrix (column-major, ldh), or the start block's R
+  int ldh;
+  int* broken;
+};
+
+template <typename T>
+void launch_cgs_pass1(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
+template <typename T>
+void launch_cgs_pass2(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
+// Small-world work after pass 1 (block step d, window i0 .. d with nw = d - i0 + 1 blocks;
+// d = 0, nw = 0 for the start block) and after pass 2.
+void launch_cgs_reduce1(int r, int nw, int i0, int d, const CgsSmall& a, const CgsSmall& b, hipStream_t st);
+void launch_cgs_reduce2(int r, int nw, int i0, int d, const CgsSmall& a, const CgsSmall& b, hipStream_t st);
+int cgs_state_doubles();
+int cgs_coef_offset();  // offset of [R1^{-1} | C_0 ..] in CgsSmall::state
 
 }  // namespace skr

@@ -84,6 +84,24 @@ __global__ void zero_small_kernel(double* small, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) small[i] = 0.0;
 }
 
+// W[(j-1) r : j r, col] <- P_j W[(j-1) r : j r, col] for blocks j = 1 .. d (W column-major,
+// leading dimension ldw; P_j row-major r x r at P + j r^2).
+__global__ void apply_pending_kernel(int r, int d, int ncol, const double* P, double* W, int ldw) {
+  const int total = d * ncol;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int j = 1 + e % d, col = e / d;
+    double* w = W + (size_t)(j - 1) * r + (size_t)col * ldw;
+    const double* Pj = P + (size_t)j * r * r;
+    double x[RMAX];
+    for (int c = 0; c < r; ++c) x[c] = w[c];
+    for (int a = 0; a < r; ++a) {
+      double t = 0.0;
+      for (int c = 0; c < r; ++c) t += Pj[a * r + c] * x[c];
+      w[a] = t;
+    }
+  }
+}
+
 int step_wgs(int n) {
   int g = ceil_div(n, 4 * WG);
   g = (g + 7) / 8 * 8;
@@ -146,6 +164,7 @@ struct Space {
   bool stored = true;
   DBuf<T> basis, work;
   DBuf<double> H, Tm, Q, small, part, skpart, w, c1, c2, wpart, ell;
+  DBuf<double> Pall, Gall, Xall, cgs;  // two-pass step: pending factors, Gram blocks, state
   DBuf<int> broken;
   DBuf<uint16_t> tab;
   T* slot(int j) const {  // 1-based basis block j
@@ -182,6 +201,7 @@ class Solver {
     SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
     SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
     ld_ = (p.maxit + 1) * r;
+    fast_ = cgs_supported(r, p.k);
     int dev = 0;
     SKR_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
@@ -278,6 +298,12 @@ class Solver {
     res->X1.alloc((size_t)sp_[0].n * ell);
     res->X2.alloc((size_t)sp_[1].n * ell);
     if (p_.recover == SKR_RECOVER_STORED) {
+      if (fast_) {  // U_j = U'_j P_j: X = sum_j U'_j (P_j W[j])
+        const int g = std::max(1, std::min(4096, ceil_div((int64_t)dfinal * ell, 256)));
+        hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sp_[0].Pall.p, W1.p, m);
+        hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sp_[1].Pall.p, W2.p, m);
+        check_launch("apply_pending");
+      }
       dense::basis_gemm<T>(sp_[0].n, r_, dfinal, ell, 1.0, sp_[0].basis.p, W1.p, m, 0.0, res->X1.p, ell, st_);
       dense::basis_gemm<T>(sp_[1].n, r_, dfinal, ell, 1.0, sp_[1].basis.p, W2.p, m, 0.0, res->X2.p, ell, st_);
     } else {
@@ -309,7 +335,18 @@ class Solver {
     s.Tm.alloc((size_t)ld_ * ld_);
     s.Q.alloc((size_t)s_ * ld_);
     s.small.alloc(SmallLayout::SIZE);
-    s.part.alloc((size_t)s.nwg * (RMAX * RMAX + 8));
+    s.part.alloc((size_t)s.nwg * std::max(RMAX * RMAX + 8, (CGS_KMAX + 1) * r_ * r_));
+    if (fast_) {
+      const size_t rr = (size_t)r_ * r_, nb = (size_t)p_.maxit + 2;
+      s.Pall.alloc(nb * rr);
+      s.Gall.alloc(nb * rr);
+      s.Xall.alloc(nb * CGS_KMAX * rr);
+      s.cgs.alloc(cgs_state_doubles());
+      s.Pall.zero(st_);
+      s.Gall.zero(st_);
+      s.Xall.zero(st_);
+      s.cgs.zero(st_);
+    }
     s.broken.alloc(1);
     s.nchunk = sketch_chunks(s.n);
     s.skpart.alloc((size_t)s.nchunk * s_ * r_);
@@ -359,7 +396,57 @@ class Solver {
     a.ldh = r_;
   }
 
+  CgsPass<T> cgs_args(Space<T>& s, int d, int nw, int i0) {
+    CgsPass<T> a{};
+    a.A = s.A;
+    a.X = d >= 1 ? s.slot(d) : nullptr;
+    a.Pd = d >= 1 ? s.Pall.p + (size_t)d * r_ * r_ : nullptr;
+    a.Y = s.work.p;
+    a.Unew = s.slot(d + 1);
+    for (int i = 0; i < nw; ++i) a.W[i] = s.slot(i0 + i);
+    a.coef = s.cgs.p + cgs_coef_offset();
+    a.part = s.part.p;
+    a.n = s.n;
+    a.nwg = s.nwg;
+    return a;
+  }
+
+  CgsSmall cgs_small(Space<T>& s, double* H, int ldh) {
+    CgsSmall m{};
+    m.part = s.part.p;
+    m.nwg = s.nwg;
+    m.Pall = s.Pall.p;
+    m.Gall = s.Gall.p;
+    m.Xall = s.Xall.p;
+    m.state = s.cgs.p;
+    m.H = H;
+    m.ldh = ldh;
+    m.broken = s.broken.p;
+    return m;
+  }
+
+  // Start block U_1 ell = C with the two-pass kernels (no window): U'_1 = C R1^{-1},
+  // ell = R2 R1, P_1 = R2^{-1}.
+  void init_two_pass(const double* C1, const double* C2) {
+    CgsPass<T> a[2];
+    const double* Cs[2] = {C1, C2};
+    for (int q = 0; q < 2; ++q) {
+      a[q] = cgs_args(sp_[q], 0, 0, 1);
+      a[q].src = Cs[q];
+    }
+    const CgsSmall m0 = cgs_small(sp_[0], sp_[0].ell.p, r_), m1 = cgs_small(sp_[1], sp_[1].ell.p, r_);
+    launch_cgs_pass1<T>(r_, 0, a[0], a[1], st_);
+    launch_cgs_reduce1(r_, 0, 1, 0, m0, m1, st_);
+    launch_cgs_pass2<T>(r_, 0, a[0], a[1], st_);
+    launch_cgs_reduce2(r_, 0, 1, 0, m0, m1, st_);
+  }
+
   void init(const double* C1, const double* C2) {
+    if (fast_) {
+      init_two_pass(C1, C2);
+      init_sketch();
+      return;
+    }
     SpaceStep<T> a0 = step_args(sp_[0], 0), a1 = step_args(sp_[1], 0);
     start_block(sp_[0], C1, a0);
     start_block(sp_[1], C2, a1);
@@ -373,6 +460,11 @@ class Solver {
     a0.Unew = sp_[0].slot(1);
     a1.Unew = sp_[1].slot(1);
     launch_normalize<T>(r_, a0, a1, st_);
+    init_sketch();
+  }
+
+  // Sketch tables, S U_1, the first whitening step and F11 = beta_1 beta_2^T.
+  void init_sketch() {
     const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
     for (int i = 0; i < 2; ++i)
       launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
@@ -394,7 +486,9 @@ class Solver {
   void sketch(int j, hipStream_t s) {
     SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].w.p, sp_[0].n, sp_[0].nchunk};
     SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].w.p, sp_[1].n, sp_[1].nchunk};
-    launch_sketch<T>(r_, (int)s_, p_.zeta, k0, k1, lds_limit_, s);
+    const size_t off = (size_t)j * r_ * r_;
+    launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, fast_ ? sp_[0].Pall.p + off : nullptr,
+                             fast_ ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
   }
 
   void whiten(int d, int step, hipStream_t s) {
@@ -403,7 +497,46 @@ class Solver {
     launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s);
   }
 
+  // Two-pass block step (r <= 4, k <= 3): pass 1 + reduce 1, pass 2 + reduce 2.
+  void block_step_two_pass(int d) {
+    const int i0 = std::max(1, d - p_.k + 1), nw = d - i0 + 1;
+    CgsPass<T> a[2];
+    for (int q = 0; q < 2; ++q) a[q] = cgs_args(sp_[q], d, nw, i0);
+    const CgsSmall m0 = cgs_small(sp_[0], sp_[0].H.p, ld_), m1 = cgs_small(sp_[1], sp_[1].H.p, ld_);
+    prof_.begin(KF_SPMM);
+    launch_cgs_pass1<T>(r_, nw, a[0], a[1], st_);
+    launch_cgs_reduce1(r_, nw, i0, d, m0, m1, st_);
+    prof_.end();
+    if (!sp_[0].stored) {
+      // ring buffer: slot(d+1) held U_{d+1-nslots}; its sketch (issued earlier on the
+      // auxiliary stream) must be complete before the slot is overwritten
+      SKR_HIP(hipStreamWaitEvent(st_, ev_sketch_, 0));
+    }
+    prof_.begin(KF_AXPY);
+    launch_cgs_pass2<T>(r_, nw, a[0], a[1], st_);
+    launch_cgs_reduce2(r_, nw, i0, d, m0, m1, st_);
+    prof_.end();
+    after_step(d);
+  }
+
+  // U_{d+1} is final: sketch it and update Q, T concurrently with the next block step.
+  void after_step(int d) {
+    SKR_HIP(hipEventRecord(ev_block_, st_));
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
+    prof_.begin(KF_SKETCH, aux_);
+    sketch(d + 1, aux_);
+    prof_.end();
+    SKR_HIP(hipEventRecord(ev_sketch_, aux_));
+    prof_.begin(KF_WHITEN, aux_);
+    whiten(d, d, aux_);
+    prof_.end();
+  }
+
   void block_step(int d) {
+    if (fast_) {
+      block_step_two_pass(d);
+      return;
+    }
     const int i0 = std::max(1, d - p_.k + 1);
     SpaceStep<T> a[2];
     for (int q = 0; q < 2; ++q) {
@@ -453,16 +586,7 @@ class Solver {
     prof_.begin(KF_NORMALIZE);
     launch_normalize<T>(r_, a[0], a[1], st_);
     prof_.end();
-    // U_{d+1} is final: sketch it and update Q, T concurrently with the next block step
-    SKR_HIP(hipEventRecord(ev_block_, st_));
-    SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
-    prof_.begin(KF_SKETCH, aux_);
-    sketch(d + 1, aux_);
-    prof_.end();
-    SKR_HIP(hipEventRecord(ev_sketch_, aux_));
-    prof_.begin(KF_WHITEN, aux_);
-    whiten(d, d, aux_);
-    prof_.end();
+    after_step(d);
   }
 
   // Two-pass recovery: regenerate U_1..U_d from C and the stored H (no inner products) and
@@ -541,6 +665,7 @@ class Solver {
   }
 
   int r_;
+  bool fast_ = false;  // two-pass block step (r <= 4, k <= 3)
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;

@@ -9,7 +9,7 @@
 namespace skr {
 enum KernelFamily { KF_SPMM = 0, KF_AXPY, KF_GRAM2, KF_NORMALIZE, KF_SKETCH, KF_WHITEN, KF_COUNT };
 inline const char* kernel_family_name(int f) {
-  static const char* names[KF_COUNT] = {"spmm_dot", "axpy_reduce", "gram2", "normalize", "sketch", "whiten"};
+  static const char* names[KF_COUNT] = {"spmm_dots", "orth_update", "gram2", "normalize", "sketch", "whiten"};
   return (f >= 0 && f < KF_COUNT) ? names[f] : "";
 }
 }  // namespace skr
