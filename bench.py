@@ -44,25 +44,26 @@ def parse():
 def algorithmic_bytes(family, cfg, w, d_avg):
     """Bytes one launch of a kernel family must move (both Krylov spaces), by its definition.
 
-    w = bulk element size.  Blocks are n x r; CSR = nnz (w + 4) + 4 (n + 1).
+    w = bulk element size, blocks are n x r, CSR = nnz (w + 4) + 4 (n + 1); k window blocks.
+    spmm: CSR streamed once, U_d read once, U~ written.  dots: U~ and the k window blocks
+    read.  update: U~ and the window read, U_{d+1} written.  sketch: U_{d+1} and the
+    2-byte embedding table (zeta entries per row) read, s x r FP64 written.  whiten: the
+    FP64 sketched basis Q (s x d r) read once.
     """
-    n, r, s = cfg["n"], cfg["r"], cfg["s"]
+    n, r, s, k = cfg["n"], cfg["r"], cfg["s"], cfg["k"]
+    blk = n * r * w
     tot = 0
     for M, diag in ((cfg["A"], cfg["sigma"] is not None), (cfg["B"], False)):
-        nnz = M.nnz
-        blk = n * r * w
-        if family == "spmm_dot":      # CSR once, U_d read, U~ written, first window block read
-            tot += nnz * (w + 4) + 4 * (n + 1) + 3 * blk + (8 * n if diag else 0)
-        elif family == "axpy_reduce":  # U~ read+written, U_i read, U_{i+1} read (averaged)
-            tot += 3 * blk + blk * (2.0 / 3.0)
-        elif family == "gram2":
-            tot += blk
-        elif family == "normalize":
-            tot += 2 * blk
-        elif family == "sketch":       # U_{d+1} read once, table read, s x r FP64 written
-            tot += blk + 2 * n * 8 + 8 * s * r
-        elif family == "whiten":       # two Gram-Schmidt passes over Q (s x d r FP64)
-            tot += 2 * 8 * s * r * d_avg
+        if family == "spmm":
+            tot += M.nnz * (w + 4) + 4 * (n + 1) + 2 * blk + (8 * n if diag else 0)
+        elif family == "dots":
+            tot += (1 + k) * blk
+        elif family == "update":
+            tot += (k + 2) * blk
+        elif family == "sketch":
+            tot += blk + 2 * 8 * n + 8 * s * r
+        elif family == "whiten":
+            tot += 8 * s * r * d_avg
     return tot
 
 
@@ -160,6 +161,9 @@ def main():
     f, a, g = last
     true_res = skr.true_residual(A, B, f.X1, f.X2, C1, C2)
     w = 4 if args.precision == "mixed" else 8
+    # the roofline kernel: the single-kernel streaming family with the most time
+    single = [f for f in ("spmm", "dots", "update") if f in fam]
+    dominant = max(single, key=lambda f: fam[f][1]) if single else dominant
     nl, ms = fam[dominant]
     d_avg = (win + 1) / 2.0
     per_launch = algorithmic_bytes(dominant, cfg, w, d_avg)
@@ -167,9 +171,12 @@ def main():
     roofline = dict(kernel=dominant, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
-    families = {k: dict(launches=v[0], avg_us=round(1000.0 * v[1] / v[0], 2),
-                        gbs=round(algorithmic_bytes(k, cfg, w, d_avg) / (v[1] / v[0] * 1e-3) / 1e9, 1))
-                for k, v in fam.items()}
+    families = {}
+    for k, v in fam.items():
+        b = algorithmic_bytes(k, cfg, w, d_avg)
+        families[k] = dict(launches=v[0], avg_us=round(1000.0 * v[1] / v[0], 2))
+        if b:
+            families[k]["gbs"] = round(b / (v[1] / v[0] * 1e-3) / 1e9, 1)
 
     out = dict(metric="Krylov tandem block steps/s at n=1M (forward + adjoint s-PKSM)", value=round(value, 2),
                unit="block steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
@@ -179,6 +186,7 @@ def main():
                                     f"{win} block steps per solve, forward + adjoint, stored-basis recovery",
                            n=cfg["n"], r=cfg["r"], k=cfg["k"], s=cfg["s"], window=win, precision=args.precision),
                roofline=roofline, kernel_families=families,
+               block_steps_per_s=round(steps_done / (split["steps"] * 1e-3), 1),
                time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
                                   projected_solves=round(split["proj"] / args.steps, 2),
                                   recovery=round(split["recover"] / args.steps, 2)),

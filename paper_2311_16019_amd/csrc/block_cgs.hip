@@ -67,45 +67,110 @@ __device__ inline Rows rows_of(const CgsPass<T>& s0, const CgsPass<T>& s1) {
   return w;
 }
 
-// Workgroup sum of NV per-thread values, written as this workgroup's partials
-// part[v * nwg + local] (value-major).  Wavefront sums by DPP, then the WG/64 wavefront
-// totals in a fixed order.
-template <int NV>
-__device__ inline void write_partials(const double (&acc)[NV], double* part, int nwg, int local, double* scratch) {
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double s = wave_sum(acc[v]);
-    if (lane == 0) scratch[wv * NV + v] = s;
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < NV; v += WG) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < WG / 64; ++w) t += scratch[w * NV + v];
-    part[(size_t)v * nwg + local] = t;
-  }
+constexpr int next_pow2(int v) { return v <= 1 ? 1 : 2 * next_pow2((v + 1) / 2); }
+
+__device__ inline double swap_sum32(double lo, double hi) {  // lanes < 32 keep lo, others hi
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+__device__ inline double swap_sum16(double lo, double hi) {  // lanes with bit 4 clear keep lo
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+template <int CTRL>
+__device__ inline double dpp_keep_sum(double lo, double hi, bool upper) {
+  const double send = upper ? lo : hi;
+  return (upper ? hi : lo) + dpp_move<CTRL>(send);
 }
 
-template <typename T, int R>
-__device__ inline void load_row(const T* __restrict__ p, int row, double (&x)[R]) {
+// Workgroup sums of NV per-thread values, written as this workgroup's partials
+// part[v * nwg + local] (value-major).  Within a wavefront the NV sums are formed by a
+// transpose-reduction: six exchange stages (lanes paired across 32, 16, mirrored 16-lane
+// rows, mirrored 8-lane halves, then quad swaps), each halving the number of values a lane
+// carries, so lane l ends with the wavefront total of value l >> (6 - log2 NV) after about
+// 2 NV exchanges instead of NV full wavefront sums.  Wavefront totals are added in order.
+template <int NV>
+__device__ inline void write_partials(const double (&acc)[NV], double* part, int nwg, int local, double* scratch) {
+  constexpr int NP = next_pow2(NV);
+  static_assert(NP <= 64, "at most 64 values");
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  double v[NP];
 #pragma unroll
-  for (int c = 0; c < R; ++c) x[c] = static_cast<double>(p[(size_t)row * R + c]);
+  for (int i = 0; i < NP; ++i) v[i] = (i < NV) ? acc[i] : 0.0;
+  int L = NP;
+  // stage 1: lanes 32 apart
+  if (L > 1) {
+#pragma unroll
+    for (int j = 0; j < NP / 2; ++j) v[j] = swap_sum32(v[j], v[j + NP / 2]);
+    L = NP / 2;
+  } else {
+    v[0] = swap_sum32(v[0], v[0]);
+  }
+  // stage 2: lanes 16 apart
+  if (NP >= 4) {
+#pragma unroll
+    for (int j = 0; j < NP / 4; ++j) v[j] = swap_sum16(v[j], v[j + NP / 4]);
+  } else {
+    v[0] = swap_sum16(v[0], v[0]);
+  }
+  // stages 3-6 within 16-lane rows: mirror (bit 3), half mirror (bit 2), quad swaps (1, 0)
+  if (NP >= 8) {
+#pragma unroll
+    for (int j = 0; j < NP / 8; ++j) v[j] = dpp_keep_sum<0x140>(v[j], v[j + NP / 8], (lane & 8) != 0);
+  } else {
+    v[0] += dpp_move<0x140>(v[0]);
+  }
+  if (NP >= 16) {
+#pragma unroll
+    for (int j = 0; j < NP / 16; ++j) v[j] = dpp_keep_sum<0x141>(v[j], v[j + NP / 16], (lane & 4) != 0);
+  } else {
+    v[0] += dpp_move<0x141>(v[0]);
+  }
+  if (NP >= 32) {
+#pragma unroll
+    for (int j = 0; j < NP / 32; ++j) v[j] = dpp_keep_sum<0x4E>(v[j], v[j + NP / 32], (lane & 2) != 0);
+  } else {
+    v[0] += dpp_move<0x4E>(v[0]);
+  }
+  if (NP >= 64) {
+    v[0] = dpp_keep_sum<0xB1>(v[0], v[1], (lane & 1) != 0);
+  } else {
+    v[0] += dpp_move<0xB1>(v[0]);
+  }
+  (void)L;
+  constexpr int SH = 6 - (NP == 1 ? 0 : (NP == 2 ? 1 : NP == 4 ? 2 : NP == 8 ? 3 : NP == 16 ? 4 : NP == 32 ? 5 : 6));
+  const int idx = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && idx < NV) scratch[wv * NV + idx] = v[0];
+  __syncthreads();
+  for (int i = threadIdx.x; i < NV; i += WG) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) t += scratch[w * NV + i];
+    part[(size_t)i * nwg + local] = t;
+  }
 }
 
 // ------------------------------------------------------------------------- pass 1
-template <typename T, int R, int NW>
-__global__ void __launch_bounds__(WG) cgs_pass1_kernel(CgsPass<T> s0, CgsPass<T> s1) {
-  constexpr int RR = R * R, NV = (NW + 1) * RR;
+// 1a: U~ = (Op U'_d) P_d (or the start block), stored in T.  Few registers, so many
+// wavefronts per CU hide the dependent row-pointer -> column -> gather loads.
+template <typename T, int R>
+__global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> s1) {
+  constexpr int RR = R * R;
   const Rows wi = rows_of(s0, s1);
   const CgsPass<T>& sp = wi.space ? s1 : s0;
   __shared__ double pd[RR];
-  __shared__ double scratch[(WG / 64) * NV];
   for (int i = threadIdx.x; i < RR; i += WG) pd[i] = sp.Pd ? sp.Pd[i] : ((i / R == i % R) ? 1.0 : 0.0);
   __syncthreads();
-  double acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const CsrView<T> A = sp.A;
   for (int base = wi.row0; base < wi.row1; base += WG) {
     const int row = base + threadIdx.x;
@@ -154,25 +219,48 @@ __global__ void __launch_bounds__(WG) cgs_pass1_kernel(CgsPass<T> s0, CgsPass<T>
         y[b] = t;
       }
     }
-    // U~ is stored in T; the products below use the stored (rounded) values
+    store_row<T, R>(sp.Y, row, y);
+  }
+}
+
+// 1b: the window products U'_i^T U~ and U~^T U~ from the stored (rounded) U~: independent
+// streaming loads, two rows per thread in flight.
+template <typename T, int R, int NW>
+__global__ void __launch_bounds__(WG) cgs_dots_kernel(CgsPass<T> s0, CgsPass<T> s1) {
+  constexpr int RR = R * R, NV = (NW + 1) * RR;
+  const Rows wi = rows_of(s0, s1);
+  const CgsPass<T>& sp = wi.space ? s1 : s0;
+  __shared__ double scratch[(WG / 64) * NV];
+  double acc[NV];
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      const T t = static_cast<T>(y[c]);
-      sp.Y[(size_t)row * R + c] = t;
-      y[c] = static_cast<double>(t);
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int base = wi.row0; base < wi.row1; base += 2 * WG) {
+    double y[2][R], w[2][NW > 0 ? NW : 1][R];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = base + h * WG + threadIdx.x;
+      const bool ok = row < wi.row1;
+      const int rr = ok ? row : wi.row0;  // rows past the end read a valid row, weighted 0
+      load_row<T, R>(sp.Y, rr, y[h]);
+#pragma unroll
+      for (int i = 0; i < NW; ++i) load_row<T, R>(sp.W[i], rr, w[h][i]);
+      if (!ok) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) y[h][c] = 0.0;
+      }
     }
 #pragma unroll
-    for (int a = 0; a < R; ++a)
-#pragma unroll
-      for (int b = 0; b < R; ++b) acc[NW * RR + a * R + b] += y[a] * y[b];
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      double w[R];
-      load_row<T, R>(sp.W[i], row, w);
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
-        for (int b = 0; b < R; ++b) acc[i * RR + a * R + b] += w[a] * y[b];
+        for (int b = 0; b < R; ++b) acc[NW * RR + a * R + b] += y[h][a] * y[h][b];
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int b = 0; b < R; ++b) acc[i * RR + a * R + b] += w[h][i][a] * y[h][b];
     }
   }
   write_partials<NV>(acc, sp.part, sp.nwg, wi.local, scratch);
@@ -191,40 +279,49 @@ __global__ void __launch_bounds__(WG) cgs_pass2_kernel(CgsPass<T> s0, CgsPass<T>
   double acc[RR];
 #pragma unroll
   for (int v = 0; v < RR; ++v) acc[v] = 0.0;
-  for (int base = wi.row0; base < wi.row1; base += WG) {
-    const int row = base + threadIdx.x;
-    if (row >= wi.row1) continue;
-    double y[R], u[R];
-    load_row<T, R>(sp.Y, row, y);
+  for (int base = wi.row0; base < wi.row1; base += 2 * WG) {  // two rows per thread in flight
+    double y[2][R], w[2][NW > 0 ? NW : 1][R];
 #pragma unroll
-    for (int b = 0; b < R; ++b) {
-      double t = 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const int row = base + h * WG + threadIdx.x;
+      const bool ok = row < wi.row1;
+      const int rr = ok ? row : wi.row0;  // rows past the end read a valid row, weighted 0
+      load_row<T, R>(sp.Y, rr, y[h]);
 #pragma unroll
-      for (int a = 0; a <= b; ++a) t += y[a] * cf[a * R + b];  // R1^{-1} is upper triangular
-      u[b] = t;
+      for (int i = 0; i < NW; ++i) load_row<T, R>(sp.W[i], rr, w[h][i]);
+      if (!ok) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) y[h][c] = 0.0;
+      }
     }
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      double w[R];
-      load_row<T, R>(sp.W[i], row, w);
+    for (int h = 0; h < 2; ++h) {
+      const int row = base + h * WG + threadIdx.x;
+      double u[R];
 #pragma unroll
       for (int b = 0; b < R; ++b) {
         double t = 0.0;
 #pragma unroll
-        for (int a = 0; a < R; ++a) t += w[a] * cf[(1 + i) * RR + a * R + b];
-        u[b] -= t;
+        for (int a = 0; a <= b; ++a) t += y[h][a] * cf[a * R + b];  // R1^{-1} is upper triangular
+        u[b] = t;
+      }
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          double t = 0.0;
+#pragma unroll
+          for (int a = 0; a < R; ++a) t += w[h][i][a] * cf[(1 + i) * RR + a * R + b];
+          u[b] -= t;
+        }
+      if (row < wi.row1) {
+        store_row<T, R>(sp.Unew, row, u);
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int b = 0; b < R; ++b) acc[a * R + b] += u[a] * u[b];
       }
     }
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      const T t = static_cast<T>(u[c]);
-      sp.Unew[(size_t)row * R + c] = t;
-      u[c] = static_cast<double>(t);
-    }
-#pragma unroll
-    for (int a = 0; a < R; ++a)
-#pragma unroll
-      for (int b = 0; b < R; ++b) acc[a * R + b] += u[a] * u[b];
   }
   write_partials<RR>(acc, sp.part, sp.nwg, wi.local, scratch);
 }
@@ -237,9 +334,16 @@ __device__ inline void sum_partials(const double* part, int nwg, int nv, double*
   double s = 0.0;
   if (v < nv) {
     const double* p = part + (size_t)v * nwg;
-    int g = sub;
-    for (; g + 48 < nwg; g += 64) s += (p[g] + p[g + 16]) + (p[g + 32] + p[g + 48]);
-    for (; g < nwg; g += 16) s += p[g];
+    for (int g0 = 0; g0 < nwg; g0 += 512) {  // 32 independent loads per thread in flight
+      double t[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int g = g0 + sub + 16 * u;
+        t[u] = (g < nwg) ? p[g] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 32; ++u) s += t[u];
+    }
   }
   s += dpp_move<0xB1>(s);
   s += dpp_move<0x4E>(s);
@@ -406,10 +510,27 @@ __global__ void __launch_bounds__(RED_T) cgs_reduce2_kernel(CgsSmall s0, CgsSmal
   }
 }
 
-template <typename T, int R, int NW>
-void pass1_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
-  hipLaunchKernelGGL((cgs_pass1_kernel<T, R, NW>), dim3(a.nwg + b.nwg), dim3(WG), 0, st, a, b);
+// Workgroups of the SpMM sweep: about four rows per thread, so that many wavefronts per CU
+// hide the dependent loads (the other sweeps use the fewer workgroups of CgsPass::nwg,
+// whose partials the reductions read).
+inline int spmm_wgs(int n) {
+  int g = ceil_div(n, 4 * WG);
+  g = (g + 7) / 8 * 8;
+  return std::max(8, std::min(2048, g));
 }
+
+template <typename T, int R, int NW>
+void spmm_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
+  CgsPass<T> a1 = a, b1 = b;
+  a1.nwg = spmm_wgs(a.n);
+  b1.nwg = spmm_wgs(b.n);
+  hipLaunchKernelGGL((cgs_spmm_kernel<T, R>), dim3(a1.nwg + b1.nwg), dim3(WG), 0, st, a1, b1);
+}
+template <typename T, int R, int NW>
+void dots_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
+  hipLaunchKernelGGL((cgs_dots_kernel<T, R, NW>), dim3(a.nwg + b.nwg), dim3(WG), 0, st, a, b);
+}
+
 template <typename T, int R, int NW>
 void pass2_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
   hipLaunchKernelGGL((cgs_pass2_kernel<T, R, NW>), dim3(a.nwg + b.nwg), dim3(WG), 0, st, a, b);
@@ -443,10 +564,21 @@ void pass2_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
 int cgs_state_doubles() { return CgsLayout::SIZE; }
 int cgs_coef_offset() { return CgsLayout::COEF; }
 
+int cgs_wgs(int n) {
+  int g = ceil_div(n, 16 * WG);
+  g = (g + 7) / 8 * 8;
+  return std::max(8, std::min(256, g));
+}
+
 template <typename T>
-void launch_cgs_pass1(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
-  SKR_CGS_DISPATCH(pass1_launch, r, nw, a, b, st);
-  check_launch("cgs_pass1");
+void launch_cgs_spmm(int r, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
+  SKR_CGS_DISPATCH(spmm_launch, r, 0, a, b, st);
+  check_launch("cgs_spmm");
+}
+template <typename T>
+void launch_cgs_dots(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
+  SKR_CGS_DISPATCH(dots_launch, r, nw, a, b, st);
+  check_launch("cgs_dots");
 }
 template <typename T>
 void launch_cgs_pass2(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
@@ -464,8 +596,10 @@ void launch_cgs_reduce2(int r, int nw, int i0, int d, const CgsSmall& a, const C
   check_launch("cgs_reduce2");
 }
 
-template void launch_cgs_pass1<double>(int, int, const CgsPass<double>&, const CgsPass<double>&, hipStream_t);
-template void launch_cgs_pass1<float>(int, int, const CgsPass<float>&, const CgsPass<float>&, hipStream_t);
+template void launch_cgs_spmm<double>(int, const CgsPass<double>&, const CgsPass<double>&, hipStream_t);
+template void launch_cgs_spmm<float>(int, const CgsPass<float>&, const CgsPass<float>&, hipStream_t);
+template void launch_cgs_dots<double>(int, int, const CgsPass<double>&, const CgsPass<double>&, hipStream_t);
+template void launch_cgs_dots<float>(int, int, const CgsPass<float>&, const CgsPass<float>&, hipStream_t);
 template void launch_cgs_pass2<double>(int, int, const CgsPass<double>&, const CgsPass<double>&, hipStream_t);
 template void launch_cgs_pass2<float>(int, int, const CgsPass<float>&, const CgsPass<float>&, hipStream_t);
 

@@ -224,8 +224,7 @@ __device__ inline void pair_reduce(PairAcc<R>& acc, double extra, double* vals, 
 
 template <typename T, int R>
 __device__ inline void load_block_row(const T* __restrict__ p, int row, double (&x)[R]) {
-#pragma unroll
-  for (int c = 0; c < R; ++c) x[c] = static_cast<double>(p[(size_t)row * R + c]);
+  load_row<T, R>(p, row, x);
 }
 
 template <typename T, int R>
@@ -472,29 +471,40 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
   }
 }
 
-// w = (sum over chunks of the partial sketches) P / sqrt(zeta); one thread per sketch row,
-// P (r x r row-major) the block's pending right factor or null for the identity.
+// w = (sum over chunks of the partial sketches) P / sqrt(zeta), P (r x r row-major) the
+// block's pending right factor or null for the identity.  Each thread sums one entry's
+// chunks (all loads in flight), then the rows of the workgroup are multiplied by P in LDS.
+constexpr int SK_CHMAX = 16;  // sketch_chunks() never exceeds this
 template <typename T>
-__global__ void sketch_reduce_kernel(SketchSpace<T> a0, SketchSpace<T> a1, const double* P0, const double* P1, int s,
-                                     int r, double scale) {
+__global__ void __launch_bounds__(256) sketch_reduce_kernel(SketchSpace<T> a0, SketchSpace<T> a1, const double* P0,
+                                                            const double* P1, int s, int r, double scale) {
   const SketchSpace<T>& sp = blockIdx.y ? a1 : a0;
   const double* P = blockIdx.y ? P1 : P0;
+  __shared__ double sh[256];
   const size_t total = (size_t)s * r;
-  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < s; row += gridDim.x * blockDim.x) {
-    double acc[RMAX];
-    for (int c = 0; c < r; ++c) {
-      double t = 0.0;
-      for (int ch = 0; ch < sp.nchunk; ++ch) t += sp.part[(size_t)ch * total + (size_t)row * r + c];
-      acc[c] = t;
+  const int rows_per = 256 / r, lr = threadIdx.x / r, c = threadIdx.x % r;
+  for (int row0 = blockIdx.x * rows_per; row0 < s; row0 += gridDim.x * rows_per) {
+    const int row = row0 + lr;
+    const bool mine = lr < rows_per && row < s;
+    double t = 0.0;
+    if (mine) {
+      double v[SK_CHMAX];
+#pragma unroll
+      for (int ch = 0; ch < SK_CHMAX; ++ch) v[ch] = (ch < sp.nchunk) ? sp.part[(size_t)ch * total + (size_t)row * r + c] : 0.0;
+#pragma unroll
+      for (int ch = 0; ch < SK_CHMAX; ++ch) t += v[ch];
     }
-    for (int b = 0; b < r; ++b) {
-      double t = acc[b];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    if (mine) {
+      double o = t;
       if (P) {
-        t = 0.0;
-        for (int c = 0; c < r; ++c) t += acc[c] * P[c * r + b];
+        o = 0.0;
+        for (int k = 0; k < r; ++k) o += sh[lr * r + k] * P[k * r + c];
       }
-      sp.w[(size_t)row * r + b] = t * scale;
+      sp.w[(size_t)row * r + c] = o * scale;
     }
+    __syncthreads();
   }
 }
 
@@ -583,8 +593,9 @@ void launch_sketch_pending(int r, int s, int zeta, const SketchSpace<T>& a, cons
     });
     check_launch("sketch");
   }
-  hipLaunchKernelGGL(sketch_reduce_kernel<T>, dim3(std::min(1024, ceil_div(s, 256)), 2), dim3(256), 0, st, a, b, Pa,
-                     Pb, s, r, 1.0 / sqrt((double)zeta));
+  SKR_REQUIRE(a.nchunk <= SK_CHMAX && b.nchunk <= SK_CHMAX, "too many sketch chunks");
+  hipLaunchKernelGGL(sketch_reduce_kernel<T>, dim3(std::min(1024, ceil_div((int64_t)s * r, 256)), 2), dim3(256), 0, st, a,
+                     b, Pa, Pb, s, r, 1.0 / sqrt((double)zeta));
   check_launch("sketch_reduce");
 }
 

@@ -113,8 +113,12 @@ struct CgsSmall {
   int* broken;
 };
 
+// Pass 1 is two sweeps: the SpMM (many workgroups) and the window products (CgsPass::nwg
+// workgroups, whose partials reduce 1 reads).
 template <typename T>
-void launch_cgs_pass1(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
+void launch_cgs_spmm(int r, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
+template <typename T>
+void launch_cgs_dots(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
 template <typename T>
 void launch_cgs_pass2(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st);
 // Small-world work after pass 1 (block step d, window i0 .. d with nw = d - i0 + 1 blocks;
@@ -123,5 +127,6 @@ void launch_cgs_reduce1(int r, int nw, int i0, int d, const CgsSmall& a, const C
 void launch_cgs_reduce2(int r, int nw, int i0, int d, const CgsSmall& a, const CgsSmall& b, hipStream_t st);
 int cgs_state_doubles();
 int cgs_coef_offset();  // offset of [R1^{-1} | C_0 ..] in CgsSmall::state
+int cgs_wgs(int n);     // workgroups per space of the sweeps that write partials
 
 }  // namespace skr

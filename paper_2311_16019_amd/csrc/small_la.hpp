@@ -59,4 +59,53 @@ __device__ inline void set_identity(double* A, int r) {
     for (int j = 0; j < r; ++j) A[i * r + j] = (i == j) ? 1.0 : 0.0;
 }
 
+// Row access of row-major n x R blocks with one vector memory instruction per 16 bytes.
+// Every block starts at a multiple of n R sizeof(T) bytes of a hipMalloc allocation, so a
+// row of R = 2 or 4 elements is aligned to its vector size.
+template <typename T, int R>
+__device__ inline void load_row(const T* __restrict__ p, int row, double (&x)[R]) {
+  const T* q = p + (size_t)row * R;
+  if constexpr (sizeof(T) == 4 && R == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(q);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else if constexpr (sizeof(T) == 4 && R == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(q);
+    x[0] = v.x; x[1] = v.y;
+  } else if constexpr (sizeof(T) == 8 && R % 2 == 0) {
+#pragma unroll
+    for (int c = 0; c < R; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(q + c);
+      x[c] = v.x; x[c + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[c] = static_cast<double>(q[c]);
+  }
+}
+
+// Stores the row rounded to T; x is replaced by the stored (rounded) values.
+template <typename T, int R>
+__device__ inline void store_row(T* __restrict__ p, int row, double (&x)[R]) {
+  T* q = p + (size_t)row * R;
+  if constexpr (sizeof(T) == 4 && R == 4) {
+    const float4 v = make_float4((float)x[0], (float)x[1], (float)x[2], (float)x[3]);
+    *reinterpret_cast<float4*>(q) = v;
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else if constexpr (sizeof(T) == 4 && R == 2) {
+    const float2 v = make_float2((float)x[0], (float)x[1]);
+    *reinterpret_cast<float2*>(q) = v;
+    x[0] = v.x; x[1] = v.y;
+  } else if constexpr (sizeof(T) == 8 && R % 2 == 0) {
+#pragma unroll
+    for (int c = 0; c < R; c += 2) *reinterpret_cast<double2*>(q + c) = make_double2(x[c], x[c + 1]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const T t = static_cast<T>(x[c]);
+      q[c] = t;
+      x[c] = static_cast<double>(t);
+    }
+  }
+}
+
 }  // namespace skr

@@ -160,6 +160,7 @@ template <typename T>
 struct Space {
   CsrView<T> A;
   int n = 0, nwg = 0, nchunk = 0;
+  int nwg2 = 0;  // workgroups of the two-pass sweeps that write partials
   int nslots = 0;
   bool stored = true;
   DBuf<T> basis, work;
@@ -327,6 +328,7 @@ class Solver {
     s.n = (int)op->n;
     s.rr = r_;
     s.nwg = step_wgs(s.n);
+    s.nwg2 = cgs_wgs(s.n);
     s.stored = (p_.recover == SKR_RECOVER_STORED);
     s.nslots = s.stored ? (p_.maxit + 1) : (p_.k + 1);
     s.basis.alloc((size_t)s.nslots * s.n * r_);
@@ -407,14 +409,14 @@ class Solver {
     a.coef = s.cgs.p + cgs_coef_offset();
     a.part = s.part.p;
     a.n = s.n;
-    a.nwg = s.nwg;
+    a.nwg = s.nwg2;
     return a;
   }
 
   CgsSmall cgs_small(Space<T>& s, double* H, int ldh) {
     CgsSmall m{};
     m.part = s.part.p;
-    m.nwg = s.nwg;
+    m.nwg = s.nwg2;
     m.Pall = s.Pall.p;
     m.Gall = s.Gall.p;
     m.Xall = s.Xall.p;
@@ -435,7 +437,8 @@ class Solver {
       a[q].src = Cs[q];
     }
     const CgsSmall m0 = cgs_small(sp_[0], sp_[0].ell.p, r_), m1 = cgs_small(sp_[1], sp_[1].ell.p, r_);
-    launch_cgs_pass1<T>(r_, 0, a[0], a[1], st_);
+    launch_cgs_spmm<T>(r_, a[0], a[1], st_);
+    launch_cgs_dots<T>(r_, 0, a[0], a[1], st_);
     launch_cgs_reduce1(r_, 0, 1, 0, m0, m1, st_);
     launch_cgs_pass2<T>(r_, 0, a[0], a[1], st_);
     launch_cgs_reduce2(r_, 0, 1, 0, m0, m1, st_);
@@ -504,7 +507,12 @@ class Solver {
     for (int q = 0; q < 2; ++q) a[q] = cgs_args(sp_[q], d, nw, i0);
     const CgsSmall m0 = cgs_small(sp_[0], sp_[0].H.p, ld_), m1 = cgs_small(sp_[1], sp_[1].H.p, ld_);
     prof_.begin(KF_SPMM);
-    launch_cgs_pass1<T>(r_, nw, a[0], a[1], st_);
+    launch_cgs_spmm<T>(r_, a[0], a[1], st_);
+    prof_.end();
+    prof_.begin(KF_DOTS);
+    launch_cgs_dots<T>(r_, nw, a[0], a[1], st_);
+    prof_.end();
+    prof_.begin(KF_REDUCE);
     launch_cgs_reduce1(r_, nw, i0, d, m0, m1, st_);
     prof_.end();
     if (!sp_[0].stored) {
@@ -512,8 +520,10 @@ class Solver {
       // auxiliary stream) must be complete before the slot is overwritten
       SKR_HIP(hipStreamWaitEvent(st_, ev_sketch_, 0));
     }
-    prof_.begin(KF_AXPY);
+    prof_.begin(KF_UPDATE);
     launch_cgs_pass2<T>(r_, nw, a[0], a[1], st_);
+    prof_.end();
+    prof_.begin(KF_REDUCE);
     launch_cgs_reduce2(r_, nw, i0, d, m0, m1, st_);
     prof_.end();
     after_step(d);
@@ -564,7 +574,7 @@ class Solver {
           a[q].Hblk = (r_ == 1) ? Hblk(s, d + 1, d) : nullptr;
         }
       }
-      prof_.begin(KF_AXPY);
+      prof_.begin(KF_DOTS);
       launch_axpy_reduce<T>(r_, a[0], a[1], st_);
       prof_.end();
     }
@@ -573,7 +583,7 @@ class Solver {
         a[q].post = POST_GRAM2;
         a[q].Hblk = Hblk(sp_[q], d + 1, d);
       }
-      prof_.begin(KF_GRAM2);
+      prof_.begin(KF_UPDATE);
       launch_gram2<T>(r_, a[0], a[1], st_);
       prof_.end();
     }
@@ -583,7 +593,7 @@ class Solver {
       // auxiliary stream) must be complete before the slot is overwritten
       SKR_HIP(hipStreamWaitEvent(st_, ev_sketch_, 0));
     }
-    prof_.begin(KF_NORMALIZE);
+    prof_.begin(KF_UPDATE);
     launch_normalize<T>(r_, a[0], a[1], st_);
     prof_.end();
     after_step(d);

@@ -7,9 +7,12 @@
 #include "proj.hpp"
 
 namespace skr {
-enum KernelFamily { KF_SPMM = 0, KF_AXPY, KF_GRAM2, KF_NORMALIZE, KF_SKETCH, KF_WHITEN, KF_COUNT };
+// Kernel families timed with HIP events when params.profile is set.  With the two-pass
+// block step "spmm", "dots" and "update" are one kernel each (the CSR block product, the
+// window products, the second sweep) and "reduce" the two small reductions of a step.
+enum KernelFamily { KF_SPMM = 0, KF_DOTS, KF_REDUCE, KF_UPDATE, KF_SKETCH, KF_WHITEN, KF_COUNT };
 inline const char* kernel_family_name(int f) {
-  static const char* names[KF_COUNT] = {"spmm_dots", "orth_update", "gram2", "normalize", "sketch", "whiten"};
+  static const char* names[KF_COUNT] = {"spmm", "dots", "reduce", "update", "sketch", "whiten"};
   return (f >= 0 && f < KF_COUNT) ? names[f] : "";
 }
 }  // namespace skr
