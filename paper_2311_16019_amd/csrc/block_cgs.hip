@@ -67,96 +67,21 @@ __device__ inline Rows rows_of(const CgsPass<T>& s0, const CgsPass<T>& s1) {
   return w;
 }
 
-constexpr int next_pow2(int v) { return v <= 1 ? 1 : 2 * next_pow2((v + 1) / 2); }
-
-__device__ inline double swap_sum32(double lo, double hi) {  // lanes < 32 keep lo, others hi
-  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
-  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
-  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
-  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
-  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
-  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
-  return x + y;
-}
-__device__ inline double swap_sum16(double lo, double hi) {  // lanes with bit 4 clear keep lo
-  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
-  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
-  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
-  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
-  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
-  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
-  return x + y;
-}
-template <int CTRL>
-__device__ inline double dpp_keep_sum(double lo, double hi, bool upper) {
-  const double send = upper ? lo : hi;
-  return (upper ? hi : lo) + dpp_move<CTRL>(send);
-}
-
 // Workgroup sums of NV per-thread values, written as this workgroup's partials
-// part[v * nwg + local] (value-major).  Within a wavefront the NV sums are formed by a
-// transpose-reduction: six exchange stages (lanes paired across 32, 16, mirrored 16-lane
-// rows, mirrored 8-lane halves, then quad swaps), each halving the number of values a lane
-// carries, so lane l ends with the wavefront total of value l >> (6 - log2 NV) after about
-// 2 NV exchanges instead of NV full wavefront sums.  Wavefront totals are added in order.
+// part[v * nwg + local] (value-major): wavefront transpose reductions, then the wavefront
+// totals added in order.
 template <int NV>
 __device__ inline void write_partials(const double (&acc)[NV], double* part, int nwg, int local, double* scratch) {
-  constexpr int NP = next_pow2(NV);
-  static_assert(NP <= 64, "at most 64 values");
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  double v[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) v[i] = (i < NV) ? acc[i] : 0.0;
-  int L = NP;
-  // stage 1: lanes 32 apart
-  if (L > 1) {
-#pragma unroll
-    for (int j = 0; j < NP / 2; ++j) v[j] = swap_sum32(v[j], v[j + NP / 2]);
-    L = NP / 2;
-  } else {
-    v[0] = swap_sum32(v[0], v[0]);
-  }
-  // stage 2: lanes 16 apart
-  if (NP >= 4) {
-#pragma unroll
-    for (int j = 0; j < NP / 4; ++j) v[j] = swap_sum16(v[j], v[j + NP / 4]);
-  } else {
-    v[0] = swap_sum16(v[0], v[0]);
-  }
-  // stages 3-6 within 16-lane rows: mirror (bit 3), half mirror (bit 2), quad swaps (1, 0)
-  if (NP >= 8) {
-#pragma unroll
-    for (int j = 0; j < NP / 8; ++j) v[j] = dpp_keep_sum<0x140>(v[j], v[j + NP / 8], (lane & 8) != 0);
-  } else {
-    v[0] += dpp_move<0x140>(v[0]);
-  }
-  if (NP >= 16) {
-#pragma unroll
-    for (int j = 0; j < NP / 16; ++j) v[j] = dpp_keep_sum<0x141>(v[j], v[j + NP / 16], (lane & 4) != 0);
-  } else {
-    v[0] += dpp_move<0x141>(v[0]);
-  }
-  if (NP >= 32) {
-#pragma unroll
-    for (int j = 0; j < NP / 32; ++j) v[j] = dpp_keep_sum<0x4E>(v[j], v[j + NP / 32], (lane & 2) != 0);
-  } else {
-    v[0] += dpp_move<0x4E>(v[0]);
-  }
-  if (NP >= 64) {
-    v[0] = dpp_keep_sum<0xB1>(v[0], v[1], (lane & 1) != 0);
-  } else {
-    v[0] += dpp_move<0xB1>(v[0]);
-  }
-  (void)L;
-  constexpr int SH = 6 - (NP == 1 ? 0 : (NP == 2 ? 1 : NP == 4 ? 2 : NP == 8 ? 3 : NP == 16 ? 4 : NP == 32 ? 5 : 6));
-  const int idx = lane >> SH;
-  if ((lane & ((1 << SH) - 1)) == 0 && idx < NV) scratch[wv * NV + idx] = v[0];
+  const int wv = threadIdx.x / 64;
+  int idx;
+  const double t = wave_transpose_sum<NV>(acc, idx);
+  if (idx >= 0) scratch[wv * NV + idx] = t;
   __syncthreads();
   for (int i = threadIdx.x; i < NV; i += WG) {
-    double t = 0.0;
+    double u = 0.0;
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) t += scratch[w * NV + i];
-    part[(size_t)i * nwg + local] = t;
+    for (int w = 0; w < WG / 64; ++w) u += scratch[w * NV + i];
+    part[(size_t)i * nwg + local] = u;
   }
 }
 

@@ -59,6 +59,88 @@ __device__ inline void set_identity(double* A, int r) {
     for (int j = 0; j < r; ++j) A[i * r + j] = (i == j) ? 1.0 : 0.0;
 }
 
+constexpr int next_pow2(int v) { return v <= 1 ? 1 : 2 * next_pow2((v + 1) / 2); }
+
+__device__ inline double swap_sum32(double lo, double hi) {  // lanes < 32 keep lo, others hi
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+__device__ inline double swap_sum16(double lo, double hi) {  // lanes with bit 4 clear keep lo
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+template <int CTRL>
+__device__ inline double dpp_keep_sum(double lo, double hi, bool upper) {
+  const double send = upper ? lo : hi;
+  return (upper ? hi : lo) + dpp_move<CTRL>(send);
+}
+
+
+// Sums over the 64 lanes of a wavefront of NV <= 64 per-lane values at once, by a transpose
+// reduction: six exchange stages (lanes paired across 32 and 16 by the gfx950 permlane swaps,
+// then mirrored 16-lane rows, mirrored 8-lane halves and quad swaps by DPP), each halving the
+// number of values a lane carries; about 2 NV exchanges instead of NV full wavefront sums.
+// Returns the total of value idx for the lane that holds it (one lane per value), idx = -1
+// for the other lanes.  All 64 lanes must be active.
+template <int NV>
+__device__ inline double wave_transpose_sum(const double (&acc)[NV], int& idx) {
+  constexpr int NP = next_pow2(NV);
+  static_assert(NP <= 64, "at most 64 values");
+  const int lane = threadIdx.x % 64;
+  double v[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) v[i] = (i < NV) ? acc[i] : 0.0;
+  if (NP >= 2) {
+#pragma unroll
+    for (int j = 0; j < NP / 2; ++j) v[j] = swap_sum32(v[j], v[j + NP / 2]);
+  } else {
+    v[0] = swap_sum32(v[0], v[0]);
+  }
+  if (NP >= 4) {
+#pragma unroll
+    for (int j = 0; j < NP / 4; ++j) v[j] = swap_sum16(v[j], v[j + NP / 4]);
+  } else {
+    v[0] = swap_sum16(v[0], v[0]);
+  }
+  if (NP >= 8) {
+#pragma unroll
+    for (int j = 0; j < NP / 8; ++j) v[j] = dpp_keep_sum<0x140>(v[j], v[j + NP / 8], (lane & 8) != 0);
+  } else {
+    v[0] += dpp_move<0x140>(v[0]);
+  }
+  if (NP >= 16) {
+#pragma unroll
+    for (int j = 0; j < NP / 16; ++j) v[j] = dpp_keep_sum<0x141>(v[j], v[j + NP / 16], (lane & 4) != 0);
+  } else {
+    v[0] += dpp_move<0x141>(v[0]);
+  }
+  if (NP >= 32) {
+#pragma unroll
+    for (int j = 0; j < NP / 32; ++j) v[j] = dpp_keep_sum<0x4E>(v[j], v[j + NP / 32], (lane & 2) != 0);
+  } else {
+    v[0] += dpp_move<0x4E>(v[0]);
+  }
+  if (NP >= 64) {
+    v[0] = dpp_keep_sum<0xB1>(v[0], v[1], (lane & 1) != 0);
+  } else {
+    v[0] += dpp_move<0xB1>(v[0]);
+  }
+  constexpr int SH = (NP == 1) ? 6 : (NP == 2) ? 5 : (NP == 4) ? 4 : (NP == 8) ? 3 : (NP == 16) ? 2 : (NP == 32) ? 1 : 0;
+  const int i = lane >> SH;
+  idx = ((lane & ((1 << SH) - 1)) == 0 && i < NV) ? i : -1;
+  return v[0];
+}
+
 // Row access of row-major n x R blocks with one vector memory instruction per 16 bytes.
 // Every block starts at a multiple of n R sizeof(T) bytes of a hipMalloc allocation, so a
 // row of R = 2 or 4 elements is aligned to its vector size.

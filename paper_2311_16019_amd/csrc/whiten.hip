@@ -3,6 +3,7 @@
 // across the threads of a wavefront.
 #include <algorithm>
 
+#include "small_la.hpp"
 #include "whiten.hpp"
 
 namespace skr {
@@ -10,94 +11,112 @@ namespace {
 
 constexpr int WT = 256;      // threads for the streaming whitening kernels
 constexpr int FT = 1024;     // threads of the finishing workgroup
-constexpr int SPLIT_COLS = 128;
+
+// ---- c = Q^T w, split over row chunks: every wavefront owns 64 / R columns of a tile of
+// 4 (64 / R) columns and sums its chunk's rows for all of them; the 64 per-lane values are
+// transpose-reduced across the wavefront, and each (chunk, column) partial is written once.
+constexpr int QT_ROWS = 256;  // rows of Q per chunk
 
 template <int R>
-constexpr int jb_of() { return R <= 4 ? 8 : (R <= 8 ? 4 : 2); }
+constexpr int qt_cols() { return 64 / R > 0 ? 64 / R : 1; }
 
 template <int R>
-__global__ void __launch_bounds__(WT) qtw_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
-  constexpr int JB = jb_of<R>();
-  const WhitenSpace& a = blockIdx.y ? a1 : a0;
-  const int j0 = blockIdx.x * JB;
-  double acc[JB][R];
-#pragma unroll
-  for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-    for (int c = 0; c < R; ++c) acc[jb][c] = 0.0;
-  for (int i = threadIdx.x; i < s; i += WT) {
-    double wr[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) wr[c] = a.w[(size_t)i * R + c];
-    double q[JB];
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) q[jb] = (j0 + jb < m) ? a.Q[(size_t)(j0 + jb) * s + i] : 0.0;
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-      for (int c = 0; c < R; ++c) acc[jb][c] += q[jb] * wr[c];
-  }
-  __shared__ double red[WT / 64][JB * R];
+__global__ void __launch_bounds__(WT) qtw_split_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+  constexpr int CW = qt_cols<R>(), NV = CW * R;
+  const WhitenSpace& a = blockIdx.z ? a1 : a0;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int j0 = (blockIdx.x * (WT / 64) + wv) * CW;
+  const int r0 = blockIdx.y * QT_ROWS, r1 = min(s, r0 + QT_ROWS);
+  double acc[NV];
 #pragma unroll
-  for (int jb = 0; jb < JB; ++jb)
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (j0 < m) {
+    for (int i = r0 + lane; i < r1; i += 64) {
+      double wr[R];
+      load_row<double, R>(a.w, i, wr);
+      double q[CW];
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      const double v = wave_sum(acc[jb][c]);
-      if (lane == 0) red[wv][jb * R + c] = v;
+      for (int jj = 0; jj < CW; ++jj) q[jj] = (j0 + jj < m) ? a.Q[(size_t)(j0 + jj) * s + i] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < CW; ++jj)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[jj * R + c] += q[jj] * wr[c];
     }
-  __syncthreads();
+  }
+  int idx;
+  const double t = wave_transpose_sum<NV>(acc, idx);
+  if (idx >= 0 && j0 + idx / R < m)
+    a.part[((size_t)blockIdx.y * m + j0 + idx / R) * R + idx % R] = t;
+}
+
+// out = sum over the row chunks of the partials (fixed order)
+__global__ void qtw_sum_kernel(WhitenSpace a0, WhitenSpace a1, int m, int r, int nchunk, int which) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
   double* out = which ? a.c2 : a.c1;
-  for (int e = threadIdx.x; e < JB * R; e += WT) {
-    const int j = j0 + e / R;
-    if (j < m) {
-      double t = 0.0;
-      for (int w = 0; w < WT / 64; ++w) t += red[w][e];
-      out[(size_t)j * R + e % R] = t;
+  const int total = m * r;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    int ch = 0;
+    for (; ch + 4 <= nchunk; ch += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] += a.part[(size_t)(ch + u) * total + e];
     }
+    for (; ch < nchunk; ++ch) t[0] += a.part[(size_t)ch * total + e];
+    out[e] = (t[0] + t[1]) + (t[2] + t[3]);
   }
 }
 
+// ---- w -= Q c in one launch: a workgroup owns 32 rows; its 8 column groups (two per
+// wavefront) take every eighth column of Q (each load a 256-byte row segment), and the 8
+// partial sums are added in order through LDS.  c is staged through LDS in column chunks.
+constexpr int QC_COLS = 512;
+constexpr int QC_ROWS = 32, QC_GROUPS = WT / QC_ROWS;
+
 template <int R>
-__global__ void __launch_bounds__(WT) qc_part_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which,
-                                                      int cols_per_split) {
-  const WhitenSpace& a = blockIdx.z ? a1 : a0;
-  const int i = blockIdx.x * WT + threadIdx.x;
-  const int j0 = blockIdx.y * cols_per_split, j1 = min(m, j0 + cols_per_split);
-  extern __shared__ double cs[];  // the split's rows of c, staged once per workgroup
+__global__ void __launch_bounds__(WT) qc_rows_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
   const double* c = which ? a.c2 : a.c1;
-  for (int e = threadIdx.x; e < (j1 - j0) * R; e += WT) cs[e] = c[(size_t)j0 * R + e];
-  __syncthreads();
-  if (i >= s) return;
+  __shared__ double cs[QC_COLS * R];
+  __shared__ double red[QC_GROUPS][QC_ROWS][R];
+  const int lr = threadIdx.x % QC_ROWS, g = threadIdx.x / QC_ROWS;
+  const int i = blockIdx.x * QC_ROWS + lr;
   double acc[R];
 #pragma unroll
   for (int cc = 0; cc < R; ++cc) acc[cc] = 0.0;
-  int j = j0;
-  for (; j + 4 <= j1; j += 4) {
-    double q[4];
+  for (int jc = 0; jc < m; jc += QC_COLS) {
+    const int jn = min(QC_COLS, m - jc);
+    __syncthreads();
+    for (int e = threadIdx.x; e < jn * R; e += WT) cs[e] = c[(size_t)jc * R + e];
+    __syncthreads();
+    if (i < s) {
+      int j = g;
+      for (; j + 3 * QC_GROUPS < jn; j += 4 * QC_GROUPS) {
+        double q[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = a.Q[(size_t)(j + u) * s + i];
+        for (int u = 0; u < 4; ++u) q[u] = a.Q[(size_t)(jc + j + QC_GROUPS * u) * s + i];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int cc = 0; cc < R; ++cc) acc[cc] += q[u] * cs[(j + u - j0) * R + cc];
+          for (int cc = 0; cc < R; ++cc) acc[cc] += q[u] * cs[(j + QC_GROUPS * u) * R + cc];
+      }
+      for (; j < jn; j += QC_GROUPS) {
+        const double q = a.Q[(size_t)(jc + j) * s + i];
+#pragma unroll
+        for (int cc = 0; cc < R; ++cc) acc[cc] += q * cs[j * R + cc];
+      }
+    }
   }
-  for (; j < j1; ++j) {
-    const double q = a.Q[(size_t)j * s + i];
 #pragma unroll
-    for (int cc = 0; cc < R; ++cc) acc[cc] += q * cs[(j - j0) * R + cc];
-  }
+  for (int cc = 0; cc < R; ++cc) red[g][lr][cc] = acc[cc];
+  __syncthreads();
+  if (g == 0 && i < s) {
 #pragma unroll
-  for (int cc = 0; cc < R; ++cc) a.part[((size_t)blockIdx.y * s + i) * R + cc] = acc[cc];
-}
-
-__global__ void wsub_kernel(WhitenSpace a0, WhitenSpace a1, int s, int r, int nsplit) {
-  const WhitenSpace& a = blockIdx.y ? a1 : a0;
-  const size_t total = (size_t)s * r;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    double t = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) t += a.part[(size_t)sp * total + e];
-    a.w[e] -= t;
+    for (int cc = 0; cc < R; ++cc) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < QC_GROUPS; ++q) t += red[q][lr][cc];
+      a.w[(size_t)i * R + cc] -= t;
+    }
   }
 }
 
@@ -141,10 +160,10 @@ __device__ void wg_gram(const double* w, int s, double* G, double* red) {
     double acc[RR];
 #pragma unroll
     for (int p = 0; p < RR; ++p) acc[p] = 0.0;
-    for (int i = tid; i < s; i += FT) {
+#pragma unroll 4
+    for (int i = tid; i < s; i += FT) {  // unrolled: several rows' loads in flight
       double x[R];
-#pragma unroll
-      for (int c = 0; c < R; ++c) x[c] = w[(size_t)i * R + c];
+      load_row<double, R>(w, i, x);
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
@@ -197,10 +216,10 @@ __global__ void __launch_bounds__(FT) whiten_finish_kernel(WhitenSpace a0, White
   }
   __syncthreads();
   if (ok) {
+#pragma unroll 4
     for (int i = tid; i < s; i += FT) {
       double x[R], y[R];
-#pragma unroll
-      for (int c = 0; c < R; ++c) x[c] = a.w[(size_t)i * R + c];
+      load_row<double, R>(a.w, i, x);
 #pragma unroll
       for (int c = 0; c < R; ++c) {
         double t = 0.0;
@@ -231,10 +250,10 @@ __global__ void __launch_bounds__(FT) whiten_finish_kernel(WhitenSpace a0, White
   }
   __syncthreads();
   // q = w R2^{-1} -> Q[:, m : m+R]
+#pragma unroll 4
   for (int i = tid; i < s; i += FT) {
     double x[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) x[c] = a.w[(size_t)i * R + c];
+    load_row<double, R>(a.w, i, x);
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       double t = 0.0;
@@ -254,10 +273,120 @@ __global__ void __launch_bounds__(FT) whiten_finish_kernel(WhitenSpace a0, White
   }
 }
 
+// Register-resident finish (R <= 4, s <= FIN_RPT FIN_T): each thread keeps its rows of w in
+// registers through both Cholesky QR passes, so w is read once and Q written once.
+constexpr int FIN_T = 512, FIN_RPT = 16;
+
+template <int R>
+__device__ inline void fin_gram(const double (&x)[FIN_RPT][R], double* G, double* red) {
+  constexpr int RR = R * R;
+  const int wv = threadIdx.x / 64;
+  double acc[RR];
+#pragma unroll
+  for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+#pragma unroll
+  for (int q = 0; q < FIN_RPT; ++q)
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) acc[a * R + b] += x[q][a] * x[q][b];
+  int idx;
+  const double t = wave_transpose_sum<RR>(acc, idx);
+  if (idx >= 0) red[wv * RR + idx] = t;
+  __syncthreads();
+  if (threadIdx.x < RR) {
+    double u = 0.0;
+    for (int w = 0; w < FIN_T / 64; ++w) u += red[w * RR + threadIdx.x];
+    G[threadIdx.x] = u;
+  }
+  __syncthreads();
+}
+
+template <int R>
+__global__ void __launch_bounds__(FIN_T) whiten_finish_reg_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m,
+                                                               int step) {
+  const WhitenSpace& a = blockIdx.x ? a1 : a0;
+  constexpr int RR = R * R;
+  __shared__ double red[(FIN_T / 64) * RR];
+  __shared__ double G[RR], R1[RR], R1i[RR], R2[RR], R2i[RR], tau[RR];
+  __shared__ int ok;
+  const int tid = threadIdx.x;
+  double x[FIN_RPT][R];
+#pragma unroll
+  for (int q = 0; q < FIN_RPT; ++q) {
+    const int i = tid + q * FIN_T;
+    if (i < s) {
+      load_row<double, R>(a.w, i, x[q]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[q][c] = 0.0;
+    }
+  }
+  fin_gram<R>(x, G, red);
+  if (tid == 0) {
+    ok = chol_upper_small(G, R1, R);
+    if (ok) inv_upper_small(R1, R1i, R);
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < FIN_RPT; ++q) {
+      double y[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k <= c; ++k) t += x[q][k] * R1i[k * R + c];
+        y[c] = t;
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[q][c] = y[c];
+    }
+    fin_gram<R>(x, G, red);
+  }
+  if (tid == 0) {
+    if (ok) ok = chol_upper_small(G, R2, R);
+    if (ok) {
+      inv_upper_small(R2, R2i, R);
+      for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) {
+          double t = 0.0;
+          for (int k = 0; k < R; ++k) t += R2[i * R + k] * R1[k * R + j];
+          tau[i * R + j] = t;
+        }
+    } else {
+      atomicMin(a.broken, step);
+      for (int i = 0; i < RR; ++i) { tau[i] = (i % (R + 1) == 0) ? 1.0 : 0.0; R2i[i] = 0.0; }
+    }
+  }
+  __syncthreads();
+  // q = (w R1^{-1}) R2^{-1} -> Q[:, m : m+R] (zero when the space broke down)
+#pragma unroll
+  for (int q = 0; q < FIN_RPT; ++q) {
+    const int i = tid + q * FIN_T;
+    if (i >= s) continue;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k <= c; ++k) t += x[q][k] * R2i[k * R + c];
+      a.Q[(size_t)(m + c) * s + i] = t;
+    }
+  }
+  for (int e = tid; e < m * R; e += FIN_T) {
+    const int i = e / R, c = e % R;
+    a.T[i + (size_t)(m + c) * a.ldt] = a.c1[e] + a.c2[e];
+  }
+  if (tid < RR) {
+    const int ra = tid / R, rb = tid % R;
+    a.T[(m + ra) + (size_t)(m + rb) * a.ldt] = (ra <= rb) ? tau[ra * R + rb] : 0.0;
+  }
+}
+
 }  // namespace
 
-int whiten_splits(int m) { return std::max(1, std::min(64, ceil_div(m, SPLIT_COLS))); }
-size_t whiten_part_doubles(int s, int r, int maxm) { return (size_t)whiten_splits(maxm) * s * r; }
+// partials of Q^T w: one m x r slab per chunk of QT_ROWS rows
+size_t whiten_part_doubles(int s, int r, int maxm) { return (size_t)ceil_div(s, QT_ROWS) * maxm * r; }
 
 #define WH_DISPATCH(r, ...)                                                \
   switch (r) {                                                             \
@@ -282,21 +411,31 @@ size_t whiten_part_doubles(int s, int r, int maxm) { return (size_t)whiten_split
 
 void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, hipStream_t st) {
   if (m > 0) {
-    const int nsplit = whiten_splits(m);
-    const int cps = ceil_div(m, nsplit);
+    const int nchunk = ceil_div(s, QT_ROWS);
     for (int pass = 0; pass < 2; ++pass) {
-      WH_DISPATCH(r, hipLaunchKernelGGL((qtw_kernel<RR_>), dim3(ceil_div(m, jb_of<RR_>()), 2), dim3(WT), 0, st, a, b, s,
-                                        m, pass));
+      WH_DISPATCH(r, {
+        const int tile = (WT / 64) * qt_cols<RR_>();
+        hipLaunchKernelGGL((qtw_split_kernel<RR_>), dim3(ceil_div(m, tile), nchunk, 2), dim3(WT), 0, st, a, b, s, m);
+      });
       check_launch("whiten_qtw");
-      WH_DISPATCH(r, hipLaunchKernelGGL((qc_part_kernel<RR_>), dim3(ceil_div(s, WT), nsplit, 2), dim3(WT),
-                                        sizeof(double) * (size_t)cps * RR_, st, a, b, s, m, pass, cps));
+      hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * r, 256)), 2), dim3(256), 0, st, a,
+                         b, m, r, nchunk, pass);
+      check_launch("whiten_qtw_sum");
+      WH_DISPATCH(r, hipLaunchKernelGGL((qc_rows_kernel<RR_>), dim3(ceil_div(s, QC_ROWS), 2), dim3(WT), 0, st, a, b, s,
+                                        m, pass));
       check_launch("whiten_qc");
-      hipLaunchKernelGGL(wsub_kernel, dim3(std::min(1024, ceil_div((int64_t)s * r, 256)), 2), dim3(256), 0, st, a, b,
-                         s, r, nsplit);
-      check_launch("whiten_sub");
     }
   }
-  WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(2), dim3(FT), 0, st, a, b, s, m, step));
+  if (r <= 4 && s <= FIN_RPT * FIN_T) {
+    switch (r) {
+      case 1: hipLaunchKernelGGL((whiten_finish_reg_kernel<1>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 2: hipLaunchKernelGGL((whiten_finish_reg_kernel<2>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 3: hipLaunchKernelGGL((whiten_finish_reg_kernel<3>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      default: hipLaunchKernelGGL((whiten_finish_reg_kernel<4>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+    }
+  } else {
+    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(2), dim3(FT), 0, st, a, b, s, m, step));
+  }
   check_launch("whiten_finish");
 }
 

@@ -14,12 +14,11 @@ struct WhitenSpace {
   double* w;      // s x r row-major: sketch of the new block, overwritten
   double* c1;     // m x r row-major: first-pass coefficients
   double* c2;     // m x r row-major: second-pass coefficients
-  double* part;   // nsplit x s x r partial products
+  double* part;   // partial products of Q^T w, one m x r slab per chunk of rows
   int* broken;    // breakdown marker of this space
   int ldt;
 };
 
-int whiten_splits(int m);
 size_t whiten_part_doubles(int s, int r, int maxm);
 
 // Append the block for step d (m = d r current columns of Q).  `init` = true builds Q_1,
