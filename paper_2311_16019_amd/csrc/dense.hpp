@@ -31,6 +31,11 @@ void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int 
 void gj_solution(int n, int nrhs, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st);
 int gj_ints(int n);
 int gj_doubles(int n);
+// y = A^{-1} b from the eliminated S of gj_eliminate(n, n, S, ...): y(i) = sum_k S(piv(i), k) b(piv(k)).
+// work holds gj_apply_doubles(n) doubles; b and y may not alias.
+void gj_apply(int n, const double* S, int lds, const int* iws, const double* b, double* y, double* work,
+              hipStream_t st);
+int gj_apply_doubles(int n);
 
 // Solve T X = B in place (B <- T^{-1} B), T upper triangular n x n, B n x nrhs.
 void trsm_left_upper(int n, int nrhs, const double* T, int ldt, double* B, int ldb, hipStream_t st);

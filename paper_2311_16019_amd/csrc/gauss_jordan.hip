@@ -360,6 +360,27 @@ __global__ void gj_gather_solution_kernel(int n, int nrhs, const double* S, int 
   }
 }
 
+// t (partial over a chunk of columns) = S(:, k0:k1) b(piv(k0:k1)); rows across threads.
+constexpr int GA_KC = 64;
+__global__ void gj_apply_part_kernel(int n, const double* S, int lds, const int* piv, const double* b, double* part) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.y * GA_KC, k1 = min(n, k0 + GA_KC);
+  if (r >= n) return;
+  double t = 0.0;
+#pragma unroll 8
+  for (int k = k0; k < k1; ++k) t += S[r + (size_t)k * lds] * b[piv[k]];
+  part[(size_t)blockIdx.y * n + r] = t;
+}
+// y(i) = sum over chunks of t(piv(i))
+__global__ void gj_apply_gather_kernel(int n, int nch, const int* piv, const double* part, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = piv[i];
+  double t = 0.0;
+  for (int c = 0; c < nch; ++c) t += part[(size_t)c * n + r];
+  y[i] = t;
+}
+
 template <int RPT, int NB>
 void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
             hipStream_t st) {
@@ -398,6 +419,16 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
 }  // namespace
 
 int gj_ints(int n) { return 3 * n; }
+int gj_apply_doubles(int n) { return ceil_div(n, GA_KC) * n; }
+
+void gj_apply(int n, const double* S, int lds, const int* iws, const double* b, double* y, double* work,
+              hipStream_t st) {
+  const int nch = ceil_div(n, GA_KC);
+  hipLaunchKernelGGL(gj_apply_part_kernel, dim3(ceil_div(n, 256), nch), dim3(256), 0, st, n, S, lds, iws, b, work);
+  check_launch("gj_apply");
+  hipLaunchKernelGGL(gj_apply_gather_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, nch, iws, work, y);
+  check_launch("gj_apply_gather");
+}
 int gj_doubles(int n) { return n + 1; }
 
 void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,

@@ -415,6 +415,8 @@ __global__ void add_kernel(int m, const double* G, int trans, double* Y) {
 
 }  // namespace
 
+constexpr int QMAX = 64;  // largest deflated subspace handled
+
 ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st_(st) {
   const size_t mm = (size_t)mmax * mmax;
   mbar_u_.alloc((size_t)(mmax + r) * mmax);
@@ -425,15 +427,21 @@ ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st
   gjd_a_.alloc(dense::gj_doubles(mmax));
   gjd_b_.alloc(dense::gj_doubles(mmax));
   lub_.alloc(mm);
-  info_.alloc(2);
+  info_.alloc(2 + QMAX);  // [rank loss, Schur, one per shifted solve]
   scal_.alloc(SCAL_N);
   scratch_.alloc(dense::scratch_doubles());
   SKR_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
   SKR_HIP(hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming));
   SKR_HIP(hipEventCreateWithFlags(&ev_aux_, hipEventDisableTiming));
+  for (auto& d : dst_) SKR_HIP(hipStreamCreateWithFlags(&d, hipStreamNonBlocking));
+  for (auto& e : dev_) SKR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 ProjSolver::~ProjSolver() {
+  for (auto d : dst_)
+    if (d) { (void)hipStreamSynchronize(d); (void)hipStreamDestroy(d); }
+  for (auto e : dev_)
+    if (e) (void)hipEventDestroy(e);
   if (aux_) (void)hipStreamSynchronize(aux_);
   if (ev_main_) (void)hipEventDestroy(ev_main_);
   if (ev_aux_) (void)hipEventDestroy(ev_aux_);
@@ -453,7 +461,6 @@ void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar) {
   dense::trsm_right_upper(m + r_, m, sp.T, ld, Mbar, ldm, st_);
 }
 
-constexpr int QMAX = 64;  // largest deflated subspace handled
 
 void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* Mst, int lms, const double* S,
                                int s_trans, const double* F11, int f_trans, int q, double* G) {
@@ -502,29 +509,54 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
   if (hinfo[1]) throw Error(SKR_EPROJ, "small Schur decomposition did not converge");
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qre, q, 0.0, Rtre, m, st_);
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qim, q, 0.0, Rtim, m, st_);
+  // The q shifted matrices K_j = [[A + a_j I, -b_j I], [b_j I, A + a_j I]] do not depend on
+  // the recurrence, so DEFL_NS of them are eliminated at a time on separate streams; the
+  // recurrence then applies each K_j^{-1} to its right-hand side in order on the solve's
+  // stream.
   const int n2 = 2 * m;
-  if (!kbuf_.p || kbuf_.n < (size_t)n2 * (n2 + 1)) {
-    kbuf_.alloc((size_t)2 * mmax_ * (2 * mmax_ + 1));
-    gjw2_.alloc(dense::gj_ints(2 * mmax_));
-    gjd2_.alloc(dense::gj_doubles(2 * mmax_));
+  if (!kb_[0].p || kb_[0].n < (size_t)n2 * n2) {
+    for (int u = 0; u < DEFL_NS; ++u) {
+      kb_[u].alloc((size_t)4 * mmax_ * mmax_);
+      gjw2_[u].alloc(dense::gj_ints(2 * mmax_));
+      gjd2_[u].alloc(dense::gj_doubles(2 * mmax_));
+    }
+    gapply_.alloc(dense::gj_apply_doubles(2 * mmax_) + 2 * (size_t)mmax_);
   }
-  for (int j = 0; j < q; ++j) {
-    hipLaunchKernelGGL(cplx_rhs_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, q, Rtre, Rtim,
-                       Zre, Zim, Tre, Tim, rhs2);
-    check_launch("cplx_rhs");
-    hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0, st_,
-                       m, Al, lal, Tre, Tim, q, j, kbuf_.p);
-    check_launch("build_shift");
-    // [K | rhs] eliminated in place; the solution overwrites rhs
-    dense::copy(n2, 1, rhs2, n2, kbuf_.p + (size_t)n2 * n2, n2, st_);
-    dense::gj_eliminate(n2, n2 + 1, kbuf_.p, n2, gjw2_.p, gjd2_.p, info_.p, nullptr, st_);
-    dense::gj_solution(n2, 1, kbuf_.p, n2, gjw2_.p, rhs2, n2, st_);
-    hipLaunchKernelGGL(split_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, rhs2, Zre, Zim);
-    check_launch("split");
+  hipStream_t ss[DEFL_NS] = {st_, aux_, dst_[0], dst_[1]};
+  double* sol = gapply_.p + dense::gj_apply_doubles(n2);  // 2m
+  for (int g0 = 0; g0 < q; g0 += DEFL_NS) {
+    const int gn = std::min(DEFL_NS, q - g0);
+    SKR_HIP(hipEventRecord(ev_main_, st_));
+    for (int u = 1; u < gn; ++u) SKR_HIP(hipStreamWaitEvent(ss[u], ev_main_, 0));
+    for (int u = 0; u < gn; ++u) {
+      const int j = g0 + u;
+      hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0,
+                         ss[u], m, Al, lal, Tre, Tim, q, j, kb_[u].p);
+      check_launch("build_shift");
+      dense::gj_eliminate(n2, n2, kb_[u].p, n2, gjw2_[u].p, gjd2_[u].p, info_.p + 2 + j, nullptr, ss[u]);
+    }
+    for (int u = 1; u < gn; ++u) {
+      SKR_HIP(hipEventRecord(dev_[u], ss[u]));
+      SKR_HIP(hipStreamWaitEvent(st_, dev_[u], 0));
+    }
+    for (int u = 0; u < gn; ++u) {
+      const int j = g0 + u;
+      hipLaunchKernelGGL(cplx_rhs_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, q, Rtre,
+                         Rtim, Zre, Zim, Tre, Tim, rhs2);
+      check_launch("cplx_rhs");
+      dense::gj_apply(n2, kb_[u].p, n2, gjw2_[u].p, rhs2, sol, gapply_.p, st_);
+      hipLaunchKernelGGL(split_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, sol, Zre, Zim);
+      check_launch("split");
+    }
   }
-  SKR_HIP(hipMemcpyAsync(hinfo, info_.p, sizeof(int), hipMemcpyDeviceToHost, st_));
-  SKR_HIP(hipStreamSynchronize(st_));
-  if (hinfo[0]) throw Error(SKR_EPROJ, "singular shifted system in the deflated solve");
+  {
+    int hq[QMAX];
+    SKR_HIP(hipMemcpyAsync(hq, info_.p + 2, q * sizeof(int), hipMemcpyDeviceToHost, st_));
+    SKR_HIP(hipStreamSynchronize(st_));
+    for (int j = 0; j < q; ++j)
+      if (hq[j]) throw Error(SKR_EPROJ, "singular shifted system in the deflated solve");
+  }
+
   // Z = Re(Zt Q^H) = Zre Qre^T + Zim Qim^T ;  G = Z L^T
   dense::gemm(false, true, m, q, q, 1.0, Zre, m, Qre, q, 0.0, Zr, m, st_);
   dense::gemm(false, true, m, q, q, 1.0, Zim, m, Qim, q, 1.0, Zr, m, st_);

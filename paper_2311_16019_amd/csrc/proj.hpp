@@ -60,8 +60,14 @@ class ProjSolver {
   DBuf<double> gjd_a_, gjd_b_;
   DBuf<double> scal_, scratch_;
   DBuf<double> acapart_, dws_, kbuf_;
-  DBuf<int> gjw2_;
-  DBuf<double> gjd2_;
+  // deflated shifted solves: DEFL_NS eliminations at a time, one stream each
+  static constexpr int DEFL_NS = 4;
+  hipStream_t dst_[DEFL_NS - 2] = {};
+  hipEvent_t dev_[DEFL_NS] = {};
+  DBuf<double> kb_[DEFL_NS];
+  DBuf<int> gjw2_[DEFL_NS];
+  DBuf<double> gjd2_[DEFL_NS];
+  DBuf<double> gapply_;
   DBuf<int> acaint_;
 };
 
