@@ -120,11 +120,23 @@ def main():
         return dict(k=cfg["k"], maxit=win, p=win, s=cfg["s"], tol=cfg["tol"], seed=cfg["sketch_seed"],
                     precision=precision, recover="stored", profile=profile)
 
+    wall = dict(forward=0.0, adjoint=0.0, grads=0.0)
+
     def one_step(precision, profile=False):
         prm = params(precision, profile)
+        t0 = time.perf_counter()
         f = skr.solve(A, B, C1, C2, **prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         a = skr.adjoint_solve(A, B, P1, P2, **prm)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        wall["forward"] += 1e3 * (t1 - t0)
+        wall["adjoint"] += 1e3 * (t2 - t1)
+        wall["grads"] += 1e3 * (t3 - t2)
         return f, a, g
 
     # warmup with every kernel family timed: find the dominant family
@@ -137,6 +149,8 @@ def main():
     dominant = max(fam_total, key=fam_total.get)
 
     torch.cuda.synchronize()
+    for key in wall:
+        wall[key] = 0.0
     t0 = time.perf_counter()
     fam = {}
     steps_done = 0
@@ -189,7 +203,10 @@ def main():
                block_steps_per_s=round(steps_done / (split["steps"] * 1e-3), 1),
                time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
                                   projected_solves=round(split["proj"] / args.steps, 2),
-                                  recovery=round(split["recover"] / args.steps, 2)),
+                                  recovery=round(split["recover"] / args.steps, 2),
+                                  forward_wall=round(wall["forward"] / args.steps, 2),
+                                  adjoint_wall=round(wall["adjoint"] / args.steps, 2),
+                                  grads_wall=round(wall["grads"] / args.steps, 2)),
                forward=dict(iters=f.iters, rho_rel=f.rho_rel, true_residual=true_res, ell=f.ell, status=f.status,
                             projected=f.proj),
                adjoint=dict(iters=a.iters, rho_rel=a.rho_rel, ell=a.ell, projected=a.proj))

@@ -194,6 +194,13 @@ SKR_API int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q,
                       double* loss, double* dC1, double* dC2, double* dsig,
                       double* dP1, double* dP2, void* stream);
 
+/* Device memory and streams released by finished calls are kept by the library and
+ * reused by later calls (a solve allocates its stored bases, gigabytes at large n, and
+ * several streams).  This returns every cached block of every device to the HIP runtime;
+ * blocks in use are unaffected.  Synchronises each device that holds cached blocks.
+ * Returns SKR_OK. */
+SKR_API int skr_release_cached_memory(void);
+
 /* Thread-local message describing the last negative return on this thread. */
 SKR_API const char* skr_last_error(void);
 

@@ -49,6 +49,11 @@ def version() -> str:
     return _lib.load().skr_version().decode()
 
 
+def release_cached_memory() -> None:
+    """Return the device memory the library keeps for reuse across calls to the HIP runtime."""
+    _lib.check(_lib.load().skr_release_cached_memory())
+
+
 class Operator:
     """A sparse operator ``M (+ diag)`` resident on the GPU (CSR of ``M`` and ``M^T``)."""
 

@@ -464,6 +464,13 @@ extern "C" int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q, c
   });
 }
 
+extern "C" int skr_release_cached_memory(void) {
+  return guarded([&] {
+    pool_trim();
+    return SKR_OK;
+  });
+}
+
 extern "C" const char* skr_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char* skr_version(void) { return "skrylov-gfx950 0.1"; }

@@ -38,21 +38,21 @@ inline void check_launch(const char* what) {
   if (e != hipSuccess) throw Error(SKR_EHIP, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
 }
 
+// Cached device allocation (see runtime.hip): blocks released with pool_free are kept and
+// handed out again; pool_trim returns the cache to the HIP runtime.
+void* pool_alloc(size_t bytes);
+void pool_free(void* p);
+void pool_trim();
+// Streams (non-blocking, default priority) kept for reuse across solves.
+hipStream_t stream_acquire();
+void stream_release(hipStream_t s);
+
 template <typename T>
 T* dmalloc(size_t count) {
-  if (count == 0) return nullptr;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(SKR_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  return static_cast<T*>(p);
+  return static_cast<T*>(pool_alloc(count * sizeof(T)));
 }
 
-inline void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
+inline void dfree(void* p) { pool_free(p); }
 
 // RAII device buffer
 template <typename T>

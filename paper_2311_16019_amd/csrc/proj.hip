@@ -430,22 +430,22 @@ ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st
   info_.alloc(2 + QMAX);  // [rank loss, Schur, one per shifted solve]
   scal_.alloc(SCAL_N);
   scratch_.alloc(dense::scratch_doubles());
-  SKR_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+  aux_ = stream_acquire();
   SKR_HIP(hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming));
   SKR_HIP(hipEventCreateWithFlags(&ev_aux_, hipEventDisableTiming));
-  for (auto& d : dst_) SKR_HIP(hipStreamCreateWithFlags(&d, hipStreamNonBlocking));
+  for (auto& d : dst_) d = stream_acquire();
   for (auto& e : dev_) SKR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 ProjSolver::~ProjSolver() {
   for (auto d : dst_)
-    if (d) { (void)hipStreamSynchronize(d); (void)hipStreamDestroy(d); }
+    if (d) { (void)hipStreamSynchronize(d); stream_release(d); }
   for (auto e : dev_)
     if (e) (void)hipEventDestroy(e);
   if (aux_) (void)hipStreamSynchronize(aux_);
   if (ev_main_) (void)hipEventDestroy(ev_main_);
   if (ev_aux_) (void)hipEventDestroy(ev_aux_);
-  if (aux_) (void)hipStreamDestroy(aux_);
+  if (aux_) stream_release(aux_);
 }
 
 void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar) {

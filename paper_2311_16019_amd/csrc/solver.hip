@@ -180,7 +180,7 @@ class Solver {
  public:
   Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
       : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
-    SKR_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+    aux_ = stream_acquire();
     SKR_HIP(hipEventCreateWithFlags(&ev_block_, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_sketch_, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_aux_done_, hipEventDisableTiming));
@@ -217,7 +217,7 @@ class Solver {
     if (ev_block_) (void)hipEventDestroy(ev_block_);
     if (ev_sketch_) (void)hipEventDestroy(ev_sketch_);
     if (ev_aux_done_) (void)hipEventDestroy(ev_aux_done_);
-    if (aux_) (void)hipStreamDestroy(aux_);
+    if (aux_) stream_release(aux_);
   }
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;

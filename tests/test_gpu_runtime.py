@@ -1,0 +1,38 @@
+"""GPU: the library's device-memory cache and stream reuse across calls.
+
+Consecutive solves take their workspaces from blocks that earlier solves released (and
+from streams they used); results must not depend on that.  Runs of one problem are compared
+with each other (FP64 LDS atomics in the embedding make runs equal only up to rounding) and
+against the oracle, with a solve of another size and a cache release in between.
+"""
+import pytest
+
+from gpu_helpers import gpu_solve, oracle_solve, product_distance
+from oracle.lowrank import rel_distance
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _dist(a, b):
+    return rel_distance(a.X1.cpu().numpy(), a.X2.cpu().numpy(), b.X1.cpu().numpy(), b.X2.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reused_workspaces_give_the_same_solution(precision):
+    import paper_2311_16019_amd as skr
+
+    cfg = make_config("convdiff2d_1000", m=37, r=4)
+    small = make_config("laplace2d_64", m=21, r=2)
+    prm = dict(k=3, maxit=24, p=8, s=800, seed=1002, tol=0.0, precision=precision)
+    print(f"runtime reuse {precision}", flush=True)
+    first, _ = gpu_solve(cfg, **prm)
+    gpu_solve(small, k=2, maxit=12, p=6, s=96, seed=7, tol=0.0, precision=precision)
+    second, _ = gpu_solve(cfg, **prm)
+    skr.release_cached_memory()
+    third, _ = gpu_solve(cfg, **prm)
+    bar = 1e-9 if precision == "fp64" else 1e-5
+    assert _dist(first, second) <= bar
+    assert _dist(first, third) <= bar
+    o = oracle_solve(cfg, **prm)
+    assert product_distance(second, o) <= (1e-6 if precision == "fp64" else 1e-4)
