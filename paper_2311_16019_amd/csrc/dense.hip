@@ -340,10 +340,143 @@ void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, 
   else run_gemm(m, n, k, LoadAT{A, lda}, LoadBT{B, ldb}, sc, st);
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// Basis products X = alpha * [U_1 ... U_nb] W + beta * X on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  A 16 x 16 x 4 product takes A(i, k) from lane i + 16 k, B(k, j)
+// from lane j + 16 k, and leaves D(4 v + g, j) in register v of lane j + 16 g.
+//
+// The reduction index q = (block, column) is walked in chunks of BG_KC.  Within a group of
+// 16 consecutive q, lane group g (= lane / 16) owns q = 4 g + s for the four MFMA steps
+// s = 0..3, so that for r a multiple of 4 a lane's four A values are one contiguous row
+// segment of one basis block (a single vector load straight from HBM, no LDS).  The W chunk
+// (BG_KC x up to 128 columns) is staged in LDS, column by column with q fastest, and each
+// lane reads its four B values of a step group as two 16-byte LDS loads.
+// Workgroup: 8 waves x 32 rows = 256 rows of X, all (<= 128) columns of one column chunk;
+// the basis is read from HBM exactly once per column chunk.
+constexpr int BG_T = 512, BG_WAVES = 8, BG_RS = 2, BG_ROWS = BG_WAVES * BG_RS * 16, BG_KC = 32;
+constexpr int BG_LDW = BG_KC + 2;  // padded LDS column of the W chunk (doubles)
+
+typedef double bg_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T, bool VEC>
+__device__ inline void bg_load_a(const T* U, int n, int r, int K, int i, int q, double a[4]) {
+  if (i >= n || q >= K) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = 0.0;
+    return;
+  }
+  if constexpr (VEC) {  // r % 4 == 0 and q % 4 == 0: four consecutive entries of one row
+    const int j = q / r, c = q - j * r;
+    const T* p = U + ((size_t)j * n + i) * r + c;
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else {
+      const double2 v0 = *reinterpret_cast<const double2*>(p);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+      a[0] = v0.x; a[1] = v0.y; a[2] = v1.x; a[3] = v1.y;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int qq = q + s;
+      const int j = qq / r, c = qq - j * r;
+      a[s] = qq < K ? static_cast<double>(U[((size_t)j * n + i) * r + c]) : 0.0;
+    }
+  }
+}
+
+template <typename T, bool VEC, int NCS>
+__global__ void __launch_bounds__(BG_T) basis_mfma_kernel(int n, int r, int K, int l, double alpha, const T* U,
+                                                          const double* W, int ldw, double beta, double* X, int ldx) {
+  __shared__ __attribute__((aligned(16))) double Ws[NCS * 16 * BG_LDW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, jl = lane & 15;
+  const int row0 = blockIdx.x * BG_ROWS + wave * (BG_RS * 16);
+  const int col0 = blockIdx.y * 128;
+  const int ncol = min(NCS * 16, l - col0);
+  bg_d4 acc[BG_RS][NCS];
+#pragma unroll
+  for (int a = 0; a < BG_RS; ++a)
+#pragma unroll
+    for (int b = 0; b < NCS; ++b) acc[a][b] = bg_d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int q0 = 0; q0 < K; q0 += BG_KC) {
+    // stage W(q0 : q0 + KC, col0 : col0 + 16 NCS) with q fastest; zeros outside
+    __syncthreads();
+    for (int e = tid; e < NCS * 16 * BG_KC; e += BG_T) {
+      const int cc = e / BG_KC, kk = e - cc * BG_KC;
+      const int q = q0 + kk;
+      Ws[cc * BG_LDW + kk] = (cc < ncol && q < K) ? W[q + (size_t)(col0 + cc) * ldw] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < BG_KC / 16; ++t) {
+      const int qg = q0 + 16 * t + 4 * g;  // this lane group's four q values: qg .. qg + 3
+      double a[BG_RS][4];
+#pragma unroll
+      for (int rs = 0; rs < BG_RS; ++rs) bg_load_a<T, VEC>(U, n, r, K, row0 + rs * 16 + jl, qg, a[rs]);
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs) {
+        const double* wp = Ws + (cs * 16 + jl) * BG_LDW + 16 * t + 4 * g;
+        const double2 b01 = *reinterpret_cast<const double2*>(wp);
+        const double2 b23 = *reinterpret_cast<const double2*>(wp + 2);
+        const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int rs = 0; rs < BG_RS; ++rs)
+            acc[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rs][s], b[s], acc[rs][cs], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int rs = 0; rs < BG_RS; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < NCS; ++cs) {
+      const int c = cs * 16 + jl;
+      if (c >= ncol) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + rs * 16 + 4 * v + g;
+        if (i >= n) continue;
+        double* p = X + (size_t)i * ldx + col0 + c;
+        *p = beta == 0.0 ? alpha * acc[rs][cs][v] : alpha * acc[rs][cs][v] + beta * *p;
+      }
+    }
+}
+
+template <typename T, bool VEC>
+void run_basis_mfma(int n, int r, int K, int l, double alpha, const T* U, const double* W, int ldw, double beta,
+                    double* X, int ldx, hipStream_t st) {
+  const int ncs = ceil_div(std::min(l, 128), 16);
+  dim3 grid(ceil_div(n, BG_ROWS), ceil_div(l, 128));
+#define SKR_BG(N)                                                                                                   \
+  hipLaunchKernelGGL((basis_mfma_kernel<T, VEC, N>), grid, dim3(BG_T), 0, st, n, r, K, l, alpha, U, W, ldw, beta, X, \
+                     ldx)
+  if (ncs <= 1) SKR_BG(1);
+  else if (ncs <= 2) SKR_BG(2);
+  else if (ncs <= 4) SKR_BG(4);
+  else SKR_BG(8);
+#undef SKR_BG
+  check_launch("basis_mfma");
+}
+
+}  // namespace
+
 template <typename T>
 void basis_gemm(int n, int r, int nb, int l, double alpha, const T* U, const double* W, int ldw, double beta,
                 double* X, int ldx, hipStream_t st) {
-  run_gemm(n, l, nb * r, LoadBasis<T>{U, n, r}, LoadBN{W, ldw}, StoreRM{X, ldx, alpha, beta}, st);
+  if (n <= 0 || l <= 0) return;
+  const int K = nb * r;
+  if (K <= 0) {
+    run_gemm(n, l, K, LoadBasis<T>{U, n, r}, LoadBN{W, ldw}, StoreRM{X, ldx, alpha, beta}, st);
+    return;
+  }
+  if (r % 4 == 0) run_basis_mfma<T, true>(n, r, K, l, alpha, U, W, ldw, beta, X, ldx, st);
+  else run_basis_mfma<T, false>(n, r, K, l, alpha, U, W, ldw, beta, X, ldx, st);
 }
 template void basis_gemm<double>(int, int, int, int, double, const double*, const double*, int, double, double*, int,
                                  hipStream_t);
