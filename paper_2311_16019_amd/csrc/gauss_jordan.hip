@@ -18,6 +18,7 @@
 // panel workgroup has one wavefront per SIMD: the per-column pivot search and broadcast
 // are latency chains, and more wavefronts would only time-share the SIMDs on them.
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "dense.hpp"
@@ -48,41 +49,59 @@ __global__ void gj_init_kernel(int n, int* used, int* info) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
 }
 
-// Pivot search key: the IEEE bits of |v| (monotone for nonnegative doubles) with the low
-// 24 bits replaced by 2^24 - 1 - row, so that the largest key is the largest modulus and,
-// among moduli equal to 28 mantissa bits, the smallest row.  Rows that may not pivot get
-// key 0; every eligible row has a key >= 1 even when its entry is zero.
-__device__ inline uint64_t pivot_key(double av, int row) {
+// Pivot search keys.  64-bit: the IEEE bits of |v| (monotone for nonnegative doubles) with
+// the low 24 bits replaced by 2^24 - 1 - row, so that the largest key is the largest
+// modulus and, among moduli equal to 28 mantissa bits, the smallest row.  32-bit (at most
+// 2048 rows): the upper word of |v| with its low 12 bits replaced by 4095 - row, which
+// resolves moduli to 8 mantissa bits: the chosen pivot is within a factor 1 - 2^-8 of the
+// column's largest eligible modulus, which keeps partial pivoting's growth bound up to that
+// factor per column.  Rows that may not pivot get key 0; every eligible row has a nonzero
+// key even when its entry is zero (the row code is at least 2048).
+__device__ inline uint64_t pivot_key(double av, int row, uint64_t) {
   const uint64_t bits = (uint64_t)__double_as_longlong(av);
   return (bits & ~0xFFFFFFull) | (uint64_t)(0xFFFFFF - row);
 }
+__device__ inline uint32_t pivot_key(double av, int row, uint32_t) {
+  const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(av) >> 32);
+  return (hi & ~0xFFFu) | (uint32_t)(0xFFF - row);
+}
 __device__ inline int key_row(uint64_t key) { return 0xFFFFFF - (int)(key & 0xFFFFFFull); }
+__device__ inline int key_row(uint32_t key) { return 0xFFF - (int)(key & 0xFFFu); }
 
 template <int CTRL>
-__device__ inline uint64_t dpp_u64(uint64_t v) {
+__device__ inline uint64_t dpp_key(uint64_t v) {
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
+template <int CTRL>
+__device__ inline uint32_t dpp_key(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline uint64_t lane_key(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint32_t lane_key(uint32_t v, int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)v, lane); }
 
 // Maximum over the wavefront, returned uniformly: butterflies within each row of 16 lanes
 // (DPP quad permutations and row rotations), then the four row maxima via readlane.
-__device__ inline uint64_t wave_max_u64(uint64_t v) {
-  uint64_t o;
-  o = dpp_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+template <typename K>
+__device__ inline K wave_max_key(K v) {
+  K o;
+  o = dpp_key<0xB1>(v);   // quad_perm [1,0,3,2]
   v = o > v ? o : v;
-  o = dpp_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+  o = dpp_key<0x4E>(v);   // quad_perm [2,3,0,1]
   v = o > v ? o : v;
-  o = dpp_u64<0x124>(v);  // row_ror:4
+  o = dpp_key<0x124>(v);  // row_ror:4
   v = o > v ? o : v;
-  o = dpp_u64<0x128>(v);  // row_ror:8
+  o = dpp_key<0x128>(v);  // row_ror:8
   v = o > v ? o : v;
-  uint64_t m = 0;
+  K m = 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * r);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * r);
-    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    const K x = lane_key(v, 16 * r);
     m = x > m ? x : m;
   }
   return m;
@@ -98,7 +117,8 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   __shared__ int pl[NB];
   __shared__ int pivl[NB];
   __shared__ double amat[NB][NB];
-  __shared__ uint64_t ckey[2][GJ_W];
+  using Key = std::conditional_t<(GJ_T * RPT <= 2048), uint32_t, uint64_t>;
+  __shared__ Key ckey[2][GJ_W];
   __shared__ double crow[2][GJ_W][NB];
   __shared__ double red[GJ_W];
   const int tid = threadIdx.x, wv = tid / 64;
@@ -118,6 +138,31 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     return;
   }
   const int k0 = g.b * NB, nbc = min(NB, g.n - k0);
+  constexpr int ROWS = GJ_T * RPT;
+  const int kp0 = k0 - NB;
+  if (g.b > 0) {
+    // The previous panel's columns S(:, K_{b-1}) (panel b-1 is always full) are staged in
+    // LDS by direct global-to-LDS loads, issued before this panel's own loads so that both
+    // sets are in flight together: sl[t * ROWS + row].  One instruction moves 128 rows of a
+    // column (16 bytes per lane) when the columns are 16-byte aligned, else 32 rows (4 bytes
+    // per lane).  A lane whose pair of rows straddles row n reads the first entry of the
+    // next column, which exists (panel b-1 is not the last column), and lands in an unused
+    // LDS row.
+    const int lane = tid % 64;
+    const bool wide = g.wide != 0;
+    const int rows_per = wide ? 128 : 32, nch = (g.n + rows_per - 1) / rows_per;
+    for (int e = wv; e < NB * nch; e += GJ_W) {
+      const int t = e / nch, j = e % nch;
+      const double* col = g.S + (size_t)(kp0 + t) * g.ld;
+      auto* dst = (__attribute__((address_space(3))) void*)(sl + t * ROWS + rows_per * j);
+      if (wide) {
+        if (rows_per * j + 2 * lane < g.n) __builtin_amdgcn_global_load_lds(col + rows_per * j + 2 * lane, dst, 16, 0, 0);
+      } else {
+        const char* cb = reinterpret_cast<const char*>(col) + 256 * j + 4 * lane;
+        if (256 * j + 4 * lane < 8 * g.n) __builtin_amdgcn_global_load_lds(cb, dst, 4, 0, 0);
+      }
+    }
+  }
   double x[RPT][NB];
   bool elig[RPT];
 #pragma unroll
@@ -127,31 +172,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     for (int c = 0; c < NB; ++c) x[q][c] = (row < g.n && c < nbc) ? g.S[row + (size_t)(k0 + c) * g.ld] : 0.0;
     elig[q] = (row < g.n) && (g.used[row] == 0);
   }
-  if (g.b > 0) {  // the previous panel (always full) applied to this panel's columns
-    // Its columns S(:, K_{b-1}) are staged in LDS by direct global-to-LDS loads (no
-    // registers, all in flight at once) into sl[t * ROWS + row]: one instruction moves 128
-    // rows of a column (16 bytes per lane) when the columns are 16-byte aligned, else 32
-    // rows (4 bytes per lane).  A lane whose pair of rows
-    // straddles row n reads the first entry of the next column, which exists (panel b-1
-    // is not the last column), and lands in an unused LDS row.
-    const int kp0 = k0 - NB;
-    constexpr int ROWS = GJ_T * RPT;
-    {
-      const int lane = tid % 64;
-      const bool wide = g.wide != 0;
-      const int rows_per = wide ? 128 : 32, nch = (g.n + rows_per - 1) / rows_per;
-      for (int e = wv; e < NB * nch; e += GJ_W) {
-        const int t = e / nch, j = e % nch;
-        const double* col = g.S + (size_t)(kp0 + t) * g.ld;
-        auto* dst = (__attribute__((address_space(3))) void*)(sl + t * ROWS + rows_per * j);
-        if (wide) {
-          if (rows_per * j + 2 * lane < g.n) __builtin_amdgcn_global_load_lds(col + rows_per * j + 2 * lane, dst, 16, 0, 0);
-        } else {
-          const char* cb = reinterpret_cast<const char*>(col) + 256 * j + 4 * lane;
-          if (256 * j + 4 * lane < 8 * g.n) __builtin_amdgcn_global_load_lds(cb, dst, 4, 0, 0);
-        }
-      }
-    }
+  if (g.b > 0) {  // the previous panel applied to this panel's columns
     if (tid < NB) pl[tid] = g.piv[kp0 + tid];
     __syncthreads();
     // amat(t, :) = S(P_{b-1}[t], K_b): the pivot rows' entries of this panel, taken from the
@@ -193,13 +214,13 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   for (int c = 0; c < NB; ++c) {
     if (c >= nbc) continue;  // uniform; keeps the loop fully unrollable
     const int buf = c & 1;
-    uint64_t key = 0;
+    Key key = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const uint64_t kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT>(q)) : 0ull;
+      const Key kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT>(q), Key{}) : Key{0};
       key = kq > key ? kq : key;
     }
-    const uint64_t wkey = wave_max_u64(key);  // uniform over the wavefront
+    const Key wkey = wave_max_key(key);  // uniform over the wavefront
     if (wkey != 0) {
       const int wr = key_row(wkey), wq = wr / GJ_T;  // wq uniform: scalar branches below
       if (wr % GJ_T == tid) {
@@ -214,11 +235,11 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
       ckey[buf][wv] = 0;
     }
     __syncthreads();
-    uint64_t gk = 0;
+    Key gk = 0;
     int gw = 0;
 #pragma unroll
     for (int w = 0; w < GJ_W; ++w) {
-      const uint64_t kw = ckey[buf][w];
+      const Key kw = ckey[buf][w];
       if (kw > gk) { gk = kw; gw = w; }
     }
     const int gr = key_row(gk);
@@ -256,6 +277,15 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
       if (!ok) atomicCAS(g.info, 0, k0 + c + 1);
     }
   }
+  // the barrier that publishes pivl comes before the panel's stores, so that it does not
+  // wait for their completion
+  __syncthreads();
+  if (tid < nbc) {
+    const int p = pivl[tid];
+    g.piv[k0 + tid] = p;
+    g.pos[p] = k0 + tid;
+    g.used[p] = 1;
+  }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int row = row_of<RPT>(q);
@@ -263,13 +293,6 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nbc) g.S[row + (size_t)(k0 + c) * g.ld] = x[q][c];
-  }
-  __syncthreads();
-  if (tid < nbc) {
-    const int p = pivl[tid];
-    g.piv[k0 + tid] = p;
-    g.pos[p] = k0 + tid;
-    g.used[p] = 1;
   }
 }
 
