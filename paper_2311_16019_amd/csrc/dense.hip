@@ -9,7 +9,7 @@ namespace skr {
 namespace dense {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, GT = 256;
+constexpr int BM = 64, BN = 64, BK = 32, GT = 256;
 
 // Element loaders: op(A)(i, k) and op(B)(k, j).  FAST selects the index that varies
 // fastest in memory so that tile loads are coalesced.
@@ -57,54 +57,99 @@ struct StoreRM {  // row-major C (element (i, j) at i*ldc + j)
   }
 };
 
+// FP64 GEMM tile on the matrix cores (v_mfma_f64_16x16x4f64; a 16 x 16 x 4 product takes
+// A(i, k) from lane i + 16 k, B(k, j) from lane j + 16 k, and leaves D(4 v + g, j) in
+// register v of lane j + 16 g).  Workgroup tile BM x BN = 64 x 64 from four wavefronts of
+// 32 x 32 (2 x 2 MFMA tiles); K in chunks of BK staged in LDS as [row][k] (k fastest, padded),
+// loaded into registers one chunk ahead.  Inside a group of 16 consecutive k, lane group
+// g = lane / 16 owns k = 4 g + s at MFMA step s, so each lane reads its four A (and B) values
+// of a group as two 16-byte LDS loads.  blockIdx.z selects a K slice of length kchunk.
+constexpr int LDK = BK + 2;
+constexpr int GPT = BM * BK / GT;  // staged elements of A (and of B) per thread
+
+typedef double gm_d4 __attribute__((ext_vector_type(4)));
+
 template <class LA, class LB, class ST>
 __global__ void __launch_bounds__(GT) gemm_kernel(int m, int n, int k, LA la, LB lb, ST st, int kchunk) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  __shared__ __attribute__((aligned(16))) double As[BM * LDK];
+  __shared__ __attribute__((aligned(16))) double Bs[BN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wr = wave >> 1, wc = wave & 1;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
   const int kb = blockIdx.z * kchunk, ke = min(k, kb + kchunk);
-  double acc[4][4];
+  gm_d4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = gm_d4{0.0, 0.0, 0.0, 0.0};
+  // staging coordinates: element e = tid + GT u of the chunk, coalesced along the fast index
+  auto a_coord = [&](int u, int& ii, int& kk) {
+    const int e = tid + GT * u;
+    if constexpr (LA::I_FAST) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+  };
+  auto b_coord = [&](int u, int& jj, int& kk) {
+    const int e = tid + GT * u;
+    if constexpr (LB::K_FAST) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
+  };
+  double ra[GPT], rb[GPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+      int ii, kk, jj, k2;
+      a_coord(u, ii, kk);
+      ra[u] = (i0 + ii < m && k0 + kk < ke) ? la(i0 + ii, k0 + kk) : 0.0;
+      b_coord(u, jj, k2);
+      rb[u] = (j0 + jj < n && k0 + k2 < ke) ? lb(k0 + k2, j0 + jj) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
   for (int k0 = kb; k0 < ke; k0 += BK) {
-#pragma unroll
-    for (int e = tid; e < BM * BK; e += GT) {
-      int ii, kk;
-      if constexpr (LA::I_FAST) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
-      const int gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < m && gk < ke) ? la(gi, gk) : 0.0;
-    }
-#pragma unroll
-    for (int e = tid; e < BN * BK; e += GT) {
-      int jj, kk;
-      if constexpr (LB::K_FAST) { kk = e % BK; jj = e / BK; } else { jj = e % BN; kk = e / BN; }
-      const int gj = j0 + jj, gk = k0 + kk;
-      Bs[kk][jj] = (gj < n && gk < ke) ? lb(gk, gj) : 0.0;
-    }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[kk][tx + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Bs[kk][ty + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    for (int u = 0; u < GPT; ++u) {
+      int ii, kk, jj, k2;
+      a_coord(u, ii, kk);
+      As[ii * LDK + kk] = ra[u];
+      b_coord(u, jj, k2);
+      Bs[jj * LDK + k2] = rb[u];
     }
     __syncthreads();
+    if (k0 + BK < ke) fetch(k0 + BK);
+#pragma unroll
+    for (int t = 0; t < BK / 16; ++t) {
+      double av[2][4], bv[2][4];
+#pragma unroll
+      for (int r2 = 0; r2 < 2; ++r2) {
+        const double* pa = As + (wr * 32 + r2 * 16 + l16) * LDK + 16 * t + 4 * g;
+        const double2 a01 = *reinterpret_cast<const double2*>(pa);
+        const double2 a23 = *reinterpret_cast<const double2*>(pa + 2);
+        av[r2][0] = a01.x; av[r2][1] = a01.y; av[r2][2] = a23.x; av[r2][3] = a23.y;
+        const double* pb = Bs + (wc * 32 + r2 * 16 + l16) * LDK + 16 * t + 4 * g;
+        const double2 b01 = *reinterpret_cast<const double2*>(pb);
+        const double2 b23 = *reinterpret_cast<const double2*>(pb + 2);
+        bv[r2][0] = b01.x; bv[r2][1] = b01.y; bv[r2][2] = b23.x; bv[r2][3] = b23.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2)
+            acc[r2][c2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r2][s], bv[c2][s], acc[r2][c2], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int r2 = 0; r2 < 2; ++r2)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + tx + 16 * u, j = j0 + ty + 16 * v;
-      if (i < m && j < n) st(i, j, acc[u][v], blockIdx.z);
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int j = j0 + wc * 32 + c2 * 16 + l16;
+      if (j >= n) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + r2 * 16 + 4 * v + g;
+        if (i < m) st(i, j, acc[r2][c2][v], blockIdx.z);
+      }
     }
 }
 
@@ -147,8 +192,7 @@ bool run_gemm_splitk(int m, int n, int k, LA la, LB lb, double alpha, double bet
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(std::min(2048, ceil_div((int64_t)m * n, 256))), dim3(256), 0, s, m, n,
                      nz, W.p, alpha, beta, C, ldc);
   check_launch("splitk_reduce");
-  SKR_HIP(hipStreamSynchronize(s));  // W is released on return
-  return true;
+  return true;  // W returns to the device-memory cache, which orders its reuse after this work
 }
 
 // ----------------------------------------------------------------------- triangular
