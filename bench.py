@@ -213,12 +213,20 @@ def main():
     if not args.no_fp64_compare and args.precision == "mixed":
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        f64, a64, _ = one_step("fp64")
+        one_step("fp64", profile=True)  # warm-up: FP64 workspaces differ from the mixed ones
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f64, a64, _ = one_step("fp64", profile=True)
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t1
         out["fp64_step"] = dict(ms=round(1000.0 * el64, 2), block_steps_per_s=round((f64.iters + a64.iters) / el64, 2),
                                 speedup_mixed_over_fp64=round(1000.0 * el64 / ms_step, 3),
-                                rho_rel=f64.rho_rel)
+                                rho_rel=f64.rho_rel,
+                                true_residual=skr.true_residual(A, B, f64.X1, f64.X2, C1, C2),
+                                time_split_ms=dict(block_steps=round(f64.ms_steps + a64.ms_steps, 2),
+                                                   projected_solves=round(f64.ms_proj + a64.ms_proj, 2),
+                                                   recovery=round(f64.ms_recover + a64.ms_recover, 2)),
+                                projected=dict(forward=f64.proj, adjoint=a64.proj))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out))

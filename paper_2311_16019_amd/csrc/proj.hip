@@ -22,6 +22,10 @@
 namespace skr {
 namespace {
 
+// Relative change of the sign iterates below which the inverses are approximated
+// (Newton-Schulz); scaling is off by then (it stops below 1e-2).
+constexpr double NS_SWITCH = 5e-3;
+
 enum Scal { LDA = 0, LDB, MU, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RES2, F2, YN2, SCAL_N };
 
 __global__ void set_scalar_kernel(double* p, double v) {
@@ -582,22 +586,49 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   const int maxit = 100;
   std::vector<double> hs(SCAL_N);
   int hinfo[2];
+  // Near convergence the inverses are replaced by the Newton-Schulz approximation
+  // X^{-1} ~ X (2I - X^2), which is the Newton step with a first-order inverse: applied to
+  // the whole block matrix Z = [[A, C], [0, -B]] it gives A' = A (3I - A^2)/2, the same for B,
+  // and C' = (C + 2C - A(AC) + (AC)B - C B^2)/2; it converges quadratically once
+  // ||I - Z^2|| < 1 and costs GEMMs only.
+  bool schulz = false;
   for (it = 0; it < maxit; ++it) {
-    // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
     SKR_HIP(hipEventRecord(ev_main_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
-    dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
-    dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
-    dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
-    SKR_HIP(hipEventRecord(ev_aux_, aux_));
-    dense::copy(m, m, a_.p, m, lu_.p, m, st_);
-    dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, s + LDA, st_);
-    dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
-    SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
-    hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
-    check_launch("mu");
-    dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
-    dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, st_);
+    if (!schulz) {
+      // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
+      dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
+      dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
+      dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
+      SKR_HIP(hipEventRecord(ev_aux_, aux_));
+      dense::copy(m, m, a_.p, m, lu_.p, m, st_);
+      dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, s + LDA, st_);
+      dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
+      SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
+      hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
+      check_launch("mu");
+      dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
+      dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, st_);
+    } else {
+      // B^2 -> lub_, B^{-1} ~ 2B - B B^2 -> bi_ on the auxiliary stream
+      dense::gemm(false, false, m, m, m, 1.0, b_.p, m, b_.p, m, 0.0, lub_.p, m, aux_);
+      dense::copy(m, m, b_.p, m, bi_.p, m, aux_);
+      dense::gemm(false, false, m, m, m, -1.0, b_.p, m, lub_.p, m, 2.0, bi_.p, m, aux_);
+      SKR_HIP(hipEventRecord(ev_aux_, aux_));
+      // A^2 -> lu_, A^{-1} ~ 2A - A A^2 -> ai_
+      dense::gemm(false, false, m, m, m, 1.0, a_.p, m, a_.p, m, 0.0, lu_.p, m, st_);
+      dense::copy(m, m, a_.p, m, ai_.p, m, st_);
+      dense::gemm(false, false, m, m, m, -1.0, a_.p, m, lu_.p, m, 2.0, ai_.p, m, st_);
+      // w2 = 2C + (AC)B - A(AC) - C B^2, the (1,2) block of Z (2I - Z^2)
+      dense::gemm(false, false, m, m, m, 1.0, a_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
+      dense::copy(m, m, c_.p, m, w2_.p, m, st_);
+      dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, b_.p, m, 2.0, w2_.p, m, st_);
+      dense::gemm(false, false, m, m, m, -1.0, a_.p, m, w1_.p, m, 1.0, w2_.p, m, st_);
+      SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
+      dense::gemm(false, false, m, m, m, -1.0, c_.p, m, lub_.p, m, 1.0, w2_.p, m, st_);
+      hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, 1.0);
+      check_launch("set_scalar");
+    }
     dense::newton_combine(m, m, s + MU, c_.p, m, w2_.p, m, c_.p, m, s + DC, s + NC, nullptr, scratch_.p, st_);
     dense::newton_combine(m, m, s + MU, a_.p, m, ai_.p, m, a_.p, m, s + DA, s + NA, s + TA, scratch_.p, st_);
     dense::newton_combine(m, m, s + MU, b_.p, m, bi_.p, m, b_.p, m, s + DB, s + NB_, s + TB, scratch_.p, st_);
@@ -612,6 +643,11 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     if (rel < 1e-2) scale = false;
     // quadratic convergence: a change below 1e-10 leaves the new iterate at rounding level
     if (rel < 1e-10) { ++it; break; }
+    if (schulz) {
+      if (rel > 0.25 * prev) schulz = false;  // not contracting quadratically: exact inverses again
+    } else if (!scale && rel < NS_SWITCH) {
+      schulz = true;
+    }
     if (extra >= 0) {
       if (--extra < 0) { ++it; break; }
     } else if (rel < 1e-6 && rel > 0.5 * prev) {
