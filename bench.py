@@ -38,7 +38,53 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="GiB: run only a plain device-to-device copy of this size (HBM counter calibration)")
     return ap.parse_args()
+
+
+# Kernel sources whose change invalidates a stored counter measurement of the SpMM kernel.
+SPMM_SOURCES = ["block_cgs.hip", "blockstep.hpp", "small_la.hpp"]
+TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                              "traffic_spmm_convdiff1000_r4_mixed.md")
+
+
+def spmm_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_16019_amd", "csrc")
+    for name in SPMM_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch from the committed counter record, or None when the record is
+    missing, is for another kernel or precision, or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if (rec.get("kernel") == kernel and rec.get("precision") == precision
+                            and rec.get("sources_sha256") == spmm_sources_digest()):
+                        return rec
+    except OSError:
+        pass
+    return None
+
+
+def copy_probe(gib):
+    import torch
+    nbytes = int(gib * (1 << 30)) // 8 * 8
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_probe_bytes=nbytes, copies=3)))
 
 
 def algorithmic_bytes(family, cfg, w, d_avg):
@@ -104,6 +150,9 @@ def main():
         print(f"bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     import torch
 
     import paper_2311_16019_amd as skr
@@ -182,8 +231,10 @@ def main():
     d_avg = (win + 1) / 2.0
     per_launch = algorithmic_bytes(dominant, cfg, w, d_avg)
     achieved = per_launch / (ms / nl * 1e-3) / 1e9
+    rec = measured_traffic(dominant, args.precision)
     roofline = dict(kernel=dominant, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=int(rec["bytes_per_launch"]) if rec else None,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
     families = {}
     for k, v in fam.items():
