@@ -49,7 +49,8 @@ enum {
 };
 
 enum { SKR_FP64 = 0, SKR_MIXED = 1 };           /* bulk precision                       */
-enum { SKR_SKETCH_SPARSE_SIGN = 0 };            /* subspace embedding                   */
+enum { SKR_SKETCH_SPARSE_SIGN = 0,             /* subspace embedding (Algorithm 1)     */
+       SKR_SKETCH_NONE = 2 };                   /* no embedding: Algorithm 2 (t-PKSM)   */
 enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
 
 /*
@@ -65,7 +66,13 @@ enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
  *   zeta      nonzeros per column of the sparse sign embedding (default 8)
  *   precision SKR_FP64, or SKR_MIXED (FP32 sparse products, orthogonalisation and sketch
  *             input; FP64 sketched quantities, projected solve and residual estimate)
- *   sketch    SKR_SKETCH_SPARSE_SIGN
+ *   sketch    SKR_SKETCH_SPARSE_SIGN: s-PKSM (Algorithm 1).  SKR_SKETCH_NONE: the truncated
+ *             Arnoldi method t-PKSM (Algorithm 2, appendix A): the same block steps without
+ *             an embedding, the projected equation H_d Y + Y G_d^T = E_1 beta_1 beta_2^T E_1^T
+ *             on the truncated block Hessenberg matrices (beta = R factors of C1, C2), the
+ *             estimate rho = sqrt(d r) (||Y E_d g_{d+1,d}^T||_F + ||h_{d+1,d} E_d^T Y||_F) of
+ *             Algorithm 2 in the stop test, and X1 = U_d Y1, X2 = V_d Y2; s, seed and zeta
+ *             are ignored.
  *   recover   SKR_RECOVER_STORED (keep every basis block in HBM) or
  *             SKR_RECOVER_TWO_PASS (keep k+1 blocks, regenerate them for the factors)
  *   profile   nonzero: record HIP events around every launch of each kernel family of

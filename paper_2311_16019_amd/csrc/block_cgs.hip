@@ -108,6 +108,31 @@ __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> 
       double yr[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) yr[c] = 0.0;
+      if (A.sell_off) {
+        // sliced ELL: a wavefront's 64 rows are one slice, so each index load (and each FP32
+        // value load) of the wavefront is one contiguous 256-byte access
+        const int q = row / SELL_C, l = row % SELL_C;
+        const int e0 = A.sell_off[q], w = (A.sell_off[q + 1] - e0) / SELL_C;
+        for (int jb = 0; jb < w; jb += 8) {
+          int cols[8];
+          double vv[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const bool ok = jb + j < w;
+            cols[j] = ok ? A.sell_col[e0 + (jb + j) * SELL_C + l] : row;
+            vv[j] = ok ? static_cast<double>(A.sell_val[e0 + (jb + j) * SELL_C + l]) : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (jb + j < w) {
+              double x[R];
+              load_row<T, R>(sp.X, cols[j], x);
+#pragma unroll
+              for (int c = 0; c < R; ++c) yr[c] += vv[j] * x[c];
+            }
+          }
+        }
+      } else {
       const int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
       // up to 8 nonzeros at a time: their indices and values, then their gathers, in flight
       for (int kb = k0; kb < k1; kb += 8) {
@@ -128,6 +153,7 @@ __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> 
             for (int c = 0; c < R; ++c) yr[c] += vv[j] * x[c];
           }
         }
+      }
       }
       if (A.diag) {
         const double dg = A.diag[row];

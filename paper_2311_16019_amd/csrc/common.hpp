@@ -43,6 +43,20 @@ inline void check_launch(const char* what) {
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 void pool_trim();
+void pool_quiet_enter();
+void pool_quiet_leave();
+// Quiet scope: once enter() is called (after the owner has waited for all device work on
+// the buffers it is about to release), releases on this host thread until the scope ends
+// need no device synchronisation before their reuse.
+struct PoolQuiet {
+  bool on = false;
+  void enter() {
+    if (!on) { pool_quiet_enter(); on = true; }
+  }
+  ~PoolQuiet() {
+    if (on) pool_quiet_leave();
+  }
+};
 // Streams (non-blocking, default priority) kept for reuse across solves.
 hipStream_t stream_acquire();
 void stream_release(hipStream_t s);

@@ -425,11 +425,8 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
                      info);
   check_launch("gj_init");
   const int lds_bytes = GJ_T * RPT * NB * (int)sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
-    attr_set = true;
-  }
+  SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds_bytes));
   for (int b = 0; b <= g.nblk; ++b) {
     g.b = b;
     const int grid = (b == 0) ? 1 : 1 + g.nupd;

@@ -1,6 +1,8 @@
 // Sparse operator creation: validation and transpose on the host, then upload.
 #include <algorithm>
+#include <climits>
 #include <memory>
+#include <vector>
 
 #include "op.hpp"
 
@@ -9,12 +11,12 @@ namespace skr {
 template <>
 CsrView<double> csr_view<double>(const skr_op_s* op, int t) {
   return {static_cast<int>(op->n), op->rowptr[t].p, op->colind[t].p, op->val64[t].p,
-          op->has_diag ? op->diag.p : nullptr};
+          op->has_diag ? op->diag.p : nullptr, op->sell_off[t].p, op->sell_col[t].p, op->sell_v64[t].p};
 }
 template <>
 CsrView<float> csr_view<float>(const skr_op_s* op, int t) {
   return {static_cast<int>(op->n), op->rowptr[t].p, op->colind[t].p, op->val32[t].p,
-          op->has_diag ? op->diag.p : nullptr};
+          op->has_diag ? op->diag.p : nullptr, op->sell_off[t].p, op->sell_col[t].p, op->sell_v32[t].p};
 }
 
 void validate_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind) {
@@ -45,6 +47,44 @@ void transpose_csr(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
       tci[pos] = static_cast<int32_t>(i);
       tv[pos] = v[k];
     }
+}
+
+// Sliced ELL with SELL_C rows per slice: slice q's width is the longest row among rows
+// q SELL_C .. q SELL_C + SELL_C - 1; entry j of its row l sits at off[q] + j SELL_C + l.
+// Returns false when the padded entry count does not fit in int32.
+bool sell_build(int64_t n, const int32_t* rp, const int32_t* ci, const double* v, std::vector<int32_t>& off,
+                std::vector<int32_t>& col, std::vector<double>& val) {
+  const int64_t ns = (n + SELL_C - 1) / SELL_C;
+  off.assign(ns + 1, 0);
+  int64_t total = 0;
+  for (int64_t q = 0; q < ns; ++q) {
+    int32_t w = 0;
+    for (int64_t i = q * SELL_C; i < std::min(n, (q + 1) * SELL_C); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+    off[q] = static_cast<int32_t>(std::min<int64_t>(total, INT32_MAX));
+    total += (int64_t)w * SELL_C;
+    if (total >= INT32_MAX) return false;
+  }
+  off[ns] = static_cast<int32_t>(total);
+  col.assign(total, 0);
+  val.assign(total, 0.0);
+  for (int64_t q = 0; q < ns; ++q) {
+    const int32_t w = (off[q + 1] - off[q]) / SELL_C;
+    for (int l = 0; l < SELL_C; ++l) {
+      const int64_t i = q * SELL_C + l;
+      for (int32_t j = 0; j < w; ++j) {
+        const int64_t e = off[q] + (int64_t)j * SELL_C + l;
+        const int32_t k = (i < n) ? rp[i] + j : 0;
+        if (i < n && k < rp[i + 1]) {
+          col[e] = ci[k];
+          val[e] = v[k];
+        } else {
+          col[e] = static_cast<int32_t>(i < n ? i : n - 1);  // padding: a valid row, value 0
+          val[e] = 0.0;
+        }
+      }
+    }
+  }
+  return true;
 }
 
 }  // namespace skr
@@ -79,6 +119,24 @@ skr_op_s* op_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t
       // the host staging buffer is reused: wait before overwriting it
       SKR_HIP(hipStreamSynchronize(stream));
     }
+  }
+  for (int t = 0; t < 2; ++t) {
+    std::vector<int32_t> off, col;
+    std::vector<double> val;
+    if (!sell_build(n, rps[t], cis[t], vs[t], off, col, val)) continue;
+    std::vector<float> val32(val.begin(), val.end());
+    op->sell_off[t].alloc(off.size());
+    op->sell_col[t].alloc(std::max<size_t>(col.size(), 1));
+    op->sell_v64[t].alloc(std::max<size_t>(val.size(), 1));
+    op->sell_v32[t].alloc(std::max<size_t>(val.size(), 1));
+    SKR_HIP(hipMemcpyAsync(op->sell_off[t].p, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    if (!col.empty()) {
+      SKR_HIP(hipMemcpyAsync(op->sell_col[t].p, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+      SKR_HIP(hipMemcpyAsync(op->sell_v64[t].p, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+      SKR_HIP(hipMemcpyAsync(op->sell_v32[t].p, val32.data(), val32.size() * sizeof(float), hipMemcpyHostToDevice,
+                             stream));
+    }
+    SKR_HIP(hipStreamSynchronize(stream));  // host staging vectors go out of scope
   }
   op->diag.alloc(n);
   if (diag) {

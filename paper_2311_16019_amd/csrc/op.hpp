@@ -11,6 +11,13 @@ struct skr_op_s {
   skr::DBuf<float> val32[2];
   skr::DBuf<double> diag;  // empty when the operator has no diagonal term
   bool has_diag = false;
+  // The same matrices sliced into ELL blocks of SELL_C consecutive rows (see sell_build):
+  // slice q holds its rows' entries column by column, entry j of row q SELL_C + l at
+  // sell_off[q] + j SELL_C + l; rows shorter than the slice's longest row are padded with
+  // zero values whose column is the row itself.
+  skr::DBuf<int32_t> sell_off[2], sell_col[2];
+  skr::DBuf<double> sell_v64[2];
+  skr::DBuf<float> sell_v32[2];
 };
 
 namespace skr {
@@ -23,7 +30,12 @@ struct CsrView {
   const int32_t* colind;
   const T* val;
   const double* diag;  // nullptr when absent
+  const int32_t* sell_off;  // sliced-ELL form of the same matrix (nullptr when absent)
+  const int32_t* sell_col;
+  const T* sell_val;
 };
+
+constexpr int SELL_C = 64;  // rows per slice: one wavefront
 
 template <typename T>
 CsrView<T> csr_view(const skr_op_s* op, int transpose);

@@ -26,7 +26,7 @@ namespace {
 // (Newton-Schulz); scaling is off by then (it stops below 1e-2).
 constexpr double NS_SWITCH = 5e-3;
 
-enum Scal { LDA = 0, LDB, MU, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RES2, F2, YN2, SCAL_N };
+enum Scal { LDA = 0, LDB, MU, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RHO2B, RES2, F2, YN2, SCAL_N };
 
 __global__ void set_scalar_kernel(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -47,10 +47,11 @@ __global__ void rhs_kernel(int m, int r, const double* F11, double* F) {
 }
 
 // rho^2 = ||hh Y[m-r:m, :]||_F^2 + ||Y[:, m-r:m] gh^T||_F^2, hh/gh r x r column-major with ld.
+// out[0] = ||hh Y(m-r:m, :)||_F^2, out[1] = ||Y(:, m-r:m) gh^T||_F^2
 __global__ void rho_kernel(int m, int r, const double* Y, const double* hh, int ldh, const double* gh, int ldg,
                            double* out) {
-  __shared__ double red[16];
-  double acc = 0.0;
+  __shared__ double red[2][16];
+  double acc[2] = {0.0, 0.0};
   for (int e = threadIdx.x; e < 2 * m * r; e += blockDim.x) {
     const int which = e / (m * r), rem = e % (m * r);
     const int a = rem % r, j = rem / r;
@@ -60,15 +61,17 @@ __global__ void rho_kernel(int m, int r, const double* Y, const double* hh, int 
     } else {  // (Y_lastcol gh^T)(j, a) = sum_c Y(j, m-r+c) gh(a, c)
       for (int c = 0; c < r; ++c) t += Y[j + (size_t)(m - r + c) * m] * gh[a + (size_t)c * ldg];
     }
-    acc += t * t;
+    acc[which] += t * t;
   }
-  acc = wave_sum(acc);
-  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
+  for (int q = 0; q < 2; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (threadIdx.x % 64 == 0) red[q][threadIdx.x / 64] = v;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 2) {
     double s = 0.0;
-    for (int w = 0; w < (int)blockDim.x / 64; ++w) s += red[w];
-    *out = s;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) s += red[threadIdx.x][w];
+    out[threadIdx.x] = s;
   }
 }
 
@@ -700,7 +703,8 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   if (stats) stats->proj_resid = pres;
   if (!(pres <= 1e-6))
     throw Error(SKR_EPROJ, "projected Sylvester residual " + std::to_string(pres) + " at d = " + std::to_string(d));
-  return std::sqrt(hs[RHO2]);
+  if (trunc_est_) return std::sqrt((double)m) * (std::sqrt(hs[RHO2]) + std::sqrt(hs[RHO2B]));
+  return std::sqrt(hs[RHO2] + hs[RHO2B]);
 }
 
 int ProjSolver::factor(double tol) {

@@ -39,6 +39,9 @@ class ProjSolver {
   // stopped when ||Y - Y1 Y2^T||_F <= tol ||Y||_F.  Returns ell; Y1, Y2 are m x ell
   // column-major with leading dimension m.
   int factor(double tol);
+  // Residual estimate of the truncated Arnoldi method (Algorithm 2):
+  // sqrt(d r) (||Y E_d g^T||_F + ||h E_d^T Y||_F) instead of sqrt of the sum of squares.
+  void use_truncated_estimate(bool on) { trunc_est_ = on; }
   const double* Y1() const { return y1_.p; }
   const double* Y2() const { return y2_.p; }
   int m() const { return m_; }
@@ -51,6 +54,7 @@ class ProjSolver {
   void deflate_right(int m, const double* Al, int lal, const double* Mst, int lms, const double* S, int s_trans,
                      const double* F11, int f_trans, int q, double* G);
   int r_, mmax_, m_ = 0;
+  bool trunc_est_ = false;
   hipStream_t st_;
   hipStream_t aux_ = nullptr;  // second stream: the two inversions of a Newton step overlap
   hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr;

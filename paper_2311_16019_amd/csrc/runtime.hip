@@ -9,8 +9,11 @@
 // Safety of reuse: a released block may still be read or written by kernels in flight on
 // any stream.  Every block that is released marks its device "dirty"; the first reuse of a
 // cached block on a dirty device synchronises the device (which is what hipFree would have
-// done at release time) and clears the mark.  A reused stream only orders new work after
-// the work already queued on it.
+// done at release time) and clears the mark.  Code that has already waited for all work on
+// the blocks it releases says so with a quiet scope (PoolQuiet): blocks released inside it
+// do not mark the device, so that concurrent solves on other host threads are not stalled
+// by a device synchronisation.  A reused stream only orders new work after the work already
+// queued on it.
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -21,6 +24,8 @@ namespace skr {
 namespace {
 
 constexpr size_t kCacheCap = size_t(64) << 30;  // cached bytes kept per device at most
+
+thread_local int tl_quiet = 0;  // depth of quiet scopes on this host thread
 constexpr int kMaxDev = 64;
 
 struct Live {
@@ -134,8 +139,11 @@ void pool_free(void* p) {
   }
   P.cached.insert({{L.dev, L.bytes}, p});
   P.cached_bytes[L.dev] += L.bytes;
-  P.dirty[L.dev] = true;
+  if (tl_quiet == 0) P.dirty[L.dev] = true;
 }
+
+void pool_quiet_enter() { ++tl_quiet; }
+void pool_quiet_leave() { --tl_quiet; }
 
 void pool_trim() {
   Pool& P = pool();

@@ -36,6 +36,12 @@ __global__ void fill_int_kernel(int* p, int v) {
 
 // beta = T_1 ell for both spaces (T column-major with ld, ell column-major r x r);
 // F11 = beta_U beta_V^T (row-major).
+// T(i, i) = 1 for i < m (column-major, leading dimension ld); other entries untouched.
+__global__ void unit_diag_kernel(int m, double* T, int ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) T[i + (size_t)i * ld] = 1.0;
+}
+
 __global__ void rhs_block_kernel(int r, const double* TU, int ldu, const double* ellU, const double* TV, int ldv,
                                  const double* ellV, double* F11) {
   __shared__ double bu[RMAX * RMAX], bv[RMAX * RMAX];
@@ -189,18 +195,22 @@ class Solver {
     SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
     SKR_REQUIRE(p.p >= 1, "p must be >= 1");
     SKR_REQUIRE(p.zeta >= 1 && p.zeta <= 64, "zeta must be in [1, 64]");
-    SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN, "only the sparse sign embedding is supported");
+    SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN || p.sketch == SKR_SKETCH_NONE,
+                "sketch must be SKR_SKETCH_SPARSE_SIGN or SKR_SKETCH_NONE");
+    sketched_ = p.sketch == SKR_SKETCH_SPARSE_SIGN;
     SKR_REQUIRE(p.recover == SKR_RECOVER_STORED || p.recover == SKR_RECOVER_TWO_PASS, "invalid recovery mode");
     SKR_REQUIRE(p.tol >= 0.0 && p.trunc_tol >= 0.0, "tolerances must be nonnegative");
-    s_ = p.s;
-    if (s_ == 0) {
-      s_ = 2 * (int64_t)p.maxit * r;
-      s_ = (s_ + p.zeta - 1) / p.zeta * p.zeta;
+    s_ = sketched_ ? p.s : 0;
+    if (sketched_) {
+      if (s_ == 0) {
+        s_ = 2 * (int64_t)p.maxit * r;
+        s_ = (s_ + p.zeta - 1) / p.zeta * p.zeta;
+      }
+      SKR_REQUIRE(s_ % p.zeta == 0, "s must be a multiple of zeta");
+      SKR_REQUIRE(s_ >= (int64_t)(p.maxit + 1) * r, "s must be at least (maxit+1) r");
+      SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
+      SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
     }
-    SKR_REQUIRE(s_ % p.zeta == 0, "s must be a multiple of zeta");
-    SKR_REQUIRE(s_ >= (int64_t)(p.maxit + 1) * r, "s must be at least (maxit+1) r");
-    SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
-    SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
     ld_ = (p.maxit + 1) * r;
     fast_ = cgs_supported(r, p.k);
     int dev = 0;
@@ -214,6 +224,8 @@ class Solver {
 
   ~Solver() {
     if (aux_) (void)hipStreamSynchronize(aux_);
+    (void)hipStreamSynchronize(st_);
+    quiet_.enter();  // every buffer below is idle now
     if (ev_block_) (void)hipEventDestroy(ev_block_);
     if (ev_sketch_) (void)hipEventDestroy(ev_sketch_);
     if (ev_aux_done_) (void)hipEventDestroy(ev_aux_done_);
@@ -230,6 +242,7 @@ class Solver {
   }
 
   skr_result_s* run(const double* C1, const double* C2) {
+    PoolQuiet quiet;  // entered once all work of this call has completed
     std::unique_ptr<skr_result_s> res(new skr_result_s());
     res->n1 = sp_[0].n;
     res->n2 = sp_[1].n;
@@ -252,6 +265,7 @@ class Solver {
     SKR_REQUIRE(rhs > 0.0 && std::isfinite(rhs), "zero or non-finite right-hand side");
 
     ProjSolver proj(r_, p_.maxit * r_, st_);
+    proj.use_truncated_estimate(!sketched_);
     int status = SKR_NOT_CONVERGED, dfinal = 0;
     double rho_rel = 0.0;
     for (int d = 1; d <= p_.maxit; ++d) {
@@ -319,6 +333,7 @@ class Solver {
     res->iters = dfinal;
     res->status = status;
     res->rho_rel = rho_rel;
+    quiet.enter();  // st_ has completed (e1); the projected solver waits for its own streams
     return res.release();
   }
 
@@ -357,7 +372,7 @@ class Solver {
     s.c2.alloc((size_t)ld_ * r_);
     s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
     s.ell.alloc((size_t)r_ * r_);
-    s.tab.alloc((size_t)s.n * p_.zeta);
+    if (sketched_) s.tab.alloc((size_t)s.n * p_.zeta);
     s.H.zero(st_);
     s.Tm.zero(st_);
     s.small.zero(st_);
@@ -468,6 +483,18 @@ class Solver {
 
   // Sketch tables, S U_1, the first whitening step and F11 = beta_1 beta_2^T.
   void init_sketch() {
+    if (!sketched_) {  // t-PKSM: T = I, so M = H and beta = ell
+      for (int i = 0; i < 2; ++i) {
+        hipLaunchKernelGGL(unit_diag_kernel, dim3(ceil_div(ld_, 256)), dim3(256), 0, st_, ld_, sp_[i].Tm.p, ld_);
+        check_launch("unit_diag");
+      }
+      F11_.alloc((size_t)r_ * r_);
+      hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p, sp_[1].Tm.p,
+                         ld_, sp_[1].ell.p, F11_.p);
+      check_launch("rhs_block");
+      rhs_block_host_.assign((size_t)r_ * r_, 0.0);
+      return;
+    }
     const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
     for (int i = 0; i < 2; ++i)
       launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
@@ -531,6 +558,7 @@ class Solver {
 
   // U_{d+1} is final: sketch it and update Q, T concurrently with the next block step.
   void after_step(int d) {
+    if (!sketched_) return;  // t-PKSM: no embedding
     SKR_HIP(hipEventRecord(ev_block_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
     prof_.begin(KF_SKETCH, aux_);
@@ -674,8 +702,10 @@ class Solver {
     flush(d);
   }
 
+  PoolQuiet quiet_;  // first member: released last, after every buffer member
   int r_;
-  bool fast_ = false;  // two-pass block step (r <= 4, k <= 3)
+  bool fast_ = false;      // two-pass block step (r <= 4, k <= 3)
+  bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;
