@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--concurrent", action="store_true",
+                    help="run the forward and the adjoint solve of a step concurrently (two host threads, "
+                         "one stream each)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB: run only a plain device-to-device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -87,30 +90,41 @@ def copy_probe(gib):
     print(json.dumps(dict(copy_probe_bytes=nbytes, copies=3)))
 
 
+SELL_C = 64  # rows per slice of the sliced-ELL operator storage
+
+
+def sell_bytes(M, w):
+    """Bytes of one sweep over M in sliced-ELL form: padded entries (values + int32 columns)
+    and the int32 slice offsets."""
+    nnz_row = np.diff(M.indptr)
+    ns = (M.shape[0] + SELL_C - 1) // SELL_C
+    padded = np.zeros(ns * SELL_C, dtype=np.int64)
+    padded[:M.shape[0]] = nnz_row
+    entries = int(padded.reshape(ns, SELL_C).max(axis=1).sum()) * SELL_C
+    return entries * (w + 4) + 4 * (ns + 1)
+
+
 def algorithmic_bytes(family, cfg, w, d_avg):
     """Bytes one launch of a kernel family must move (both Krylov spaces), by its definition.
 
-    w = bulk element size, blocks are n x r, CSR = nnz (w + 4) + 4 (n + 1); k window blocks.
-    spmm: CSR streamed once, U_d read once, U~ written.  dots: U~ and the k window blocks
+    w = bulk element size, blocks are n x r; k window blocks.  spmm: the operator in its
+    sliced-ELL form streamed once (padded entries (w + 4) + 4 (slices + 1), the mean of the
+    forward orientations A, B^T and the adjoint ones A^T, B), U_d read once, U~ written,
+    the diagonal shift of A read.  dots: U~ and the k window blocks
     read.  update: U~ and the window read, U_{d+1} written.  sketch: U_{d+1} and the
     2-byte embedding table (zeta entries per row) read, s x r FP64 written.  whiten: the
     FP64 sketched basis Q (s x d r) read once.
     """
     n, r, s, k = cfg["n"], cfg["r"], cfg["s"], cfg["k"]
     blk = n * r * w
-    tot = 0
-    for M, diag in ((cfg["A"], cfg["sigma"] is not None), (cfg["B"], False)):
-        if family == "spmm":
-            tot += M.nnz * (w + 4) + 4 * (n + 1) + 2 * blk + (8 * n if diag else 0)
-        elif family == "dots":
-            tot += (1 + k) * blk
-        elif family == "update":
-            tot += (k + 2) * blk
-        elif family == "sketch":
-            tot += blk + 2 * 8 * n + 8 * s * r
-        elif family == "whiten":
-            tot += 8 * s * r * d_avg
-    return tot
+    if family == "spmm":
+        a, b = cfg["A"].to_scipy(), cfg["B"].to_scipy()
+        ops = [sell_bytes(M, w) for M in (a, b.T.tocsr(), a.T.tocsr(), b)]
+        diag = 8 * n if cfg["sigma"] is not None else 0
+        return (ops[0] + ops[1] + ops[2] + ops[3]) / 2 + 2 * (2 * blk) + diag
+    per_space = {"dots": (1 + k) * blk, "update": (k + 2) * blk, "sketch": blk + 2 * 8 * n + 8 * s * r,
+                 "whiten": 8 * s * r * d_avg}
+    return 2 * per_space.get(family, 0)
 
 
 def cpu_baseline(cfg, steps):
@@ -169,10 +183,33 @@ def main():
         return dict(k=cfg["k"], maxit=win, p=win, s=cfg["s"], tol=cfg["tol"], seed=cfg["sketch_seed"],
                     precision=precision, recover="stored", profile=profile)
 
-    wall = dict(forward=0.0, adjoint=0.0, grads=0.0)
+    wall = dict(forward=0.0, adjoint=0.0, grads=0.0, solves=0.0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
+    pool = None
+    if args.concurrent:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=2)
+
+    def on_stream(st, fn, *a, **kw):
+        with torch.cuda.stream(st):
+            return fn(*a, stream=st, **kw)
 
     def one_step(precision, profile=False):
         prm = params(precision, profile)
+        if pool is not None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ff = pool.submit(on_stream, streams[0], skr.solve, A, B, C1, C2, **prm)
+            fa = pool.submit(on_stream, streams[1], skr.adjoint_solve, A, B, P1, P2, **prm)
+            f, a = ff.result(), fa.result()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            wall["solves"] += 1e3 * (t2 - t0)
+            wall["grads"] += 1e3 * (t3 - t2)
+            return f, a, g
         t0 = time.perf_counter()
         f = skr.solve(A, B, C1, C2, **prm)
         torch.cuda.synchronize()
@@ -185,6 +222,7 @@ def main():
         t3 = time.perf_counter()
         wall["forward"] += 1e3 * (t1 - t0)
         wall["adjoint"] += 1e3 * (t2 - t1)
+        wall["solves"] += 1e3 * (t2 - t0)
         wall["grads"] += 1e3 * (t3 - t2)
         return f, a, g
 
@@ -255,9 +293,9 @@ def main():
                time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
                                   projected_solves=round(split["proj"] / args.steps, 2),
                                   recovery=round(split["recover"] / args.steps, 2),
-                                  forward_wall=round(wall["forward"] / args.steps, 2),
-                                  adjoint_wall=round(wall["adjoint"] / args.steps, 2),
+                                  solves_wall=round(wall["solves"] / args.steps, 2),
                                   grads_wall=round(wall["grads"] / args.steps, 2)),
+               schedule="forward and adjoint concurrent" if args.concurrent else "forward, then adjoint",
                forward=dict(iters=f.iters, rho_rel=f.rho_rel, true_residual=true_res, ell=f.ell, status=f.status,
                             projected=f.proj),
                adjoint=dict(iters=a.iters, rho_rel=a.rho_rel, ell=a.ell, projected=a.proj))
@@ -278,6 +316,22 @@ def main():
                                                    projected_solves=round(f64.ms_proj + a64.ms_proj, 2),
                                                    recovery=round(f64.ms_recover + a64.ms_recover, 2)),
                                 projected=dict(forward=f64.proj, adjoint=a64.proj))
+    # Algorithm 2 (t-PKSM: the same block steps with no embedding) on the same forward
+    # problem and window, for comparison with s-PKSM
+    prm_t = params(args.precision, profile=True)
+    prm_t["sketch"] = "none"
+    skr.solve(A, B, C1, C2, **prm_t)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ft = skr.solve(A, B, C1, C2, **prm_t)
+    torch.cuda.synchronize()
+    elt = time.perf_counter() - t1
+    out["tpksm_forward"] = dict(ms=round(1000.0 * elt, 2), block_steps_per_s=round(ft.iters / elt, 1),
+                                time_split_ms=dict(block_steps=round(ft.ms_steps, 2),
+                                                   projected_solves=round(ft.ms_proj, 2),
+                                                   recovery=round(ft.ms_recover, 2)),
+                                rho_rel=ft.rho_rel, true_residual=skr.true_residual(A, B, ft.X1, ft.X2, C1, C2),
+                                projected=ft.proj)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out))

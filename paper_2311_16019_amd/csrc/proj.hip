@@ -9,9 +9,11 @@
 // identity (all eigenvalues in the open right half plane, the case of the positive real
 // operators this solver targets).  Every iteration is two Gauss-Jordan inversions and two GEMMs,
 // which map onto the GPU; the paper solves the same equation with Bartels-Stewart (Sec. 6),
-// whose Schur decompositions do not.  When a limit is not the identity the projected
-// matrix is indefinite (the paper's Example 4.5 shows this can happen) and the solve
-// reports SKR_EPROJ rather than return a wrong Y.
+// whose Schur decompositions do not.  Near convergence the inversions are replaced by
+// Newton-Schulz steps (GEMMs only).  When a limit is not the identity the projected matrix
+// is indefinite (the paper's Example 4.5 shows this can happen); the traces of the limits
+// count the eigenvalues in the left half plane, and the part of Y on them is added by a
+// spectral deflation (below).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -404,6 +406,20 @@ __global__ void build_shift_kernel(int m, const double* A, int lda, const double
   }
 }
 
+// K (m x m) = A + a I with a = Re T(j, j)
+__global__ void build_real_shift_kernel(int m, const double* A, int lda, const double* Tre, int q, int j, double* K) {
+  const double a = Tre[j + j * q];
+  const size_t total = (size_t)m * m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), k = (int)(e / m);
+    K[e] = A[i + (size_t)k * lda] + (i == k ? a : 0.0);
+  }
+}
+
+__global__ void negate_kernel(int m, double* x) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) x[e] = -x[e];
+}
+
 __global__ void split_kernel(int m, int j, const double* x, double* Zre, double* Zim) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
     Zre[e + (size_t)j * m] = x[e];
@@ -516,46 +532,100 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
   if (hinfo[1]) throw Error(SKR_EPROJ, "small Schur decomposition did not converge");
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qre, q, 0.0, Rtre, m, st_);
   dense::gemm(false, false, m, q, q, 1.0, RHS, m, Qim, q, 0.0, Rtim, m, st_);
-  // The q shifted matrices K_j = [[A + a_j I, -b_j I], [b_j I, A + a_j I]] do not depend on
-  // the recurrence, so DEFL_NS of them are eliminated at a time on separate streams; the
-  // recurrence then applies each K_j^{-1} to its right-hand side in order on the solve's
-  // stream.
+  // Shifted solves (A + lambda_j I) z_j = rhs_j, lambda_j = a_j + i b_j the diagonal of the
+  // complex Schur form, in the order of the recurrence.  The matrices do not depend on the
+  // recurrence, so they are eliminated first, DEFL_NS at a time on separate streams, and the
+  // recurrence then only applies the inverses.  A real matrix's eigenvalues come in
+  // conjugate pairs, and K(conj lambda) = P K(lambda) P with P = diag(I, -I) for the real
+  // form K(lambda) = [[A + a I, -b I], [b I, A + a I]], so one elimination serves both
+  // members of a pair (the second applies it with the imaginary halves negated); a real
+  // shift needs only the m x m matrix A + a I, applied to the real and imaginary parts.
+  std::vector<double> hT(2 * (size_t)q * q);
+  SKR_HIP(hipMemcpyAsync(hT.data(), Tre, sizeof(double) * q * q, hipMemcpyDeviceToHost, st_));
+  SKR_HIP(hipMemcpyAsync(hT.data() + (size_t)q * q, Tim, sizeof(double) * q * q, hipMemcpyDeviceToHost, st_));
+  SKR_HIP(hipStreamSynchronize(st_));
   const int n2 = 2 * m;
-  if (!kb_[0].p || kb_[0].n < (size_t)n2 * n2) {
-    for (int u = 0; u < DEFL_NS; ++u) {
-      kb_[u].alloc((size_t)4 * mmax_ * mmax_);
-      gjw2_[u].alloc(dense::gj_ints(2 * mmax_));
-      gjd2_[u].alloc(dense::gj_doubles(2 * mmax_));
-    }
-    gapply_.alloc(dense::gj_apply_doubles(2 * mmax_) + 2 * (size_t)mmax_);
-  }
   hipStream_t ss[DEFL_NS] = {st_, aux_, dst_[0], dst_[1]};
+  if (!gapply_.p || gapply_.n < dense::gj_apply_doubles(2 * mmax_) + 2 * (size_t)mmax_)
+    gapply_.alloc(dense::gj_apply_doubles(2 * mmax_) + 2 * (size_t)mmax_);
   double* sol = gapply_.p + dense::gj_apply_doubles(n2);  // 2m
-  for (int g0 = 0; g0 < q; g0 += DEFL_NS) {
-    const int gn = std::min(DEFL_NS, q - g0);
-    SKR_HIP(hipEventRecord(ev_main_, st_));
-    for (int u = 1; u < gn; ++u) SKR_HIP(hipStreamWaitEvent(ss[u], ev_main_, 0));
-    for (int u = 0; u < gn; ++u) {
-      const int j = g0 + u;
-      hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0,
-                         ss[u], m, Al, lal, Tre, Tim, q, j, kb_[u].p);
-      check_launch("build_shift");
-      dense::gj_eliminate(n2, n2, kb_[u].p, n2, gjw2_[u].p, gjd2_[u].p, info_.p + 2 + j, nullptr, ss[u]);
+  struct Rep { int j; bool real; };
+  std::vector<Rep> reps;           // eliminations of the current chunk of the recurrence
+  std::vector<int> use_rep(q), use_flip(q);
+  auto flush = [&](int j0, int j1) {  // eliminate the chunk's matrices, then run j0 .. j1-1
+    const int nr = (int)reps.size();
+    while ((int)kbv_.size() < nr) {
+      kbv_.emplace_back();
+      gjwv_.emplace_back();
+      gjdv_.emplace_back();
     }
-    for (int u = 1; u < gn; ++u) {
+    SKR_HIP(hipEventRecord(ev_main_, st_));
+    for (int u = 1; u < std::min(nr, (int)DEFL_NS); ++u) SKR_HIP(hipStreamWaitEvent(ss[u], ev_main_, 0));
+    for (int u = 0; u < nr; ++u) {
+      const int nn = reps[u].real ? m : n2, j = reps[u].j;
+      if (kbv_[u].n < (size_t)4 * mmax_ * mmax_) {
+        kbv_[u].alloc((size_t)4 * mmax_ * mmax_);
+        gjwv_[u].alloc(dense::gj_ints(2 * mmax_));
+        gjdv_[u].alloc(dense::gj_doubles(2 * mmax_));
+      }
+      hipStream_t su = ss[u % DEFL_NS];
+      if (reps[u].real)
+        hipLaunchKernelGGL(build_real_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)m * m, 256))), dim3(256), 0,
+                           su, m, Al, lal, Tre, q, j, kbv_[u].p);
+      else
+        hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0,
+                           su, m, Al, lal, Tre, Tim, q, j, kbv_[u].p);
+      check_launch("build_shift");
+      dense::gj_eliminate(nn, nn, kbv_[u].p, nn, gjwv_[u].p, gjdv_[u].p, info_.p + 2 + j, nullptr, su);
+    }
+    for (int u = 1; u < std::min(nr, (int)DEFL_NS); ++u) {
       SKR_HIP(hipEventRecord(dev_[u], ss[u]));
       SKR_HIP(hipStreamWaitEvent(st_, dev_[u], 0));
     }
-    for (int u = 0; u < gn; ++u) {
-      const int j = g0 + u;
-      hipLaunchKernelGGL(cplx_rhs_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, q, Rtre,
-                         Rtim, Zre, Zim, Tre, Tim, rhs2);
+    const int gm = std::min(1024, ceil_div(m, 256));
+    for (int j = j0; j < j1; ++j) {
+      const int u = use_rep[j];
+      hipLaunchKernelGGL(cplx_rhs_kernel, dim3(gm), dim3(256), 0, st_, m, j, q, Rtre, Rtim, Zre, Zim, Tre, Tim, rhs2);
       check_launch("cplx_rhs");
-      dense::gj_apply(n2, kb_[u].p, n2, gjw2_[u].p, rhs2, sol, gapply_.p, st_);
-      hipLaunchKernelGGL(split_kernel, dim3(std::min(1024, ceil_div(m, 256))), dim3(256), 0, st_, m, j, sol, Zre, Zim);
+      if (reps[u].real) {
+        dense::gj_apply(m, kbv_[u].p, m, gjwv_[u].p, rhs2, sol, gapply_.p, st_);
+        dense::gj_apply(m, kbv_[u].p, m, gjwv_[u].p, rhs2 + m, sol + m, gapply_.p, st_);
+      } else {
+        if (use_flip[j]) hipLaunchKernelGGL(negate_kernel, dim3(gm), dim3(256), 0, st_, m, rhs2 + m);
+        dense::gj_apply(n2, kbv_[u].p, n2, gjwv_[u].p, rhs2, sol, gapply_.p, st_);
+        if (use_flip[j]) hipLaunchKernelGGL(negate_kernel, dim3(gm), dim3(256), 0, st_, m, sol + m);
+      }
+      hipLaunchKernelGGL(split_kernel, dim3(gm), dim3(256), 0, st_, m, j, sol, Zre, Zim);
       check_launch("split");
     }
+    reps.clear();
+  };
+  constexpr int REP_CHUNK = 16;  // eliminated matrices held at once
+  int j0 = 0;
+  for (int j = 0; j < q; ++j) {
+    const double a = hT[j + (size_t)j * q], b = hT[(size_t)q * q + j + (size_t)j * q];
+    const double sc = std::max({std::fabs(a), std::fabs(b), 1e-300});
+    const bool real = std::fabs(b) <= 1e-13 * sc;
+    int u = -1, flip = 0;
+    for (int v = 0; v < (int)reps.size() && u < 0; ++v) {
+      const int i = reps[v].j;
+      const double ai = hT[i + (size_t)i * q], bi = hT[(size_t)q * q + i + (size_t)i * q];
+      if (reps[v].real != real || std::fabs(a - ai) > 1e-12 * sc) continue;
+      if (real || std::fabs(b - bi) <= 1e-12 * sc) u = v;
+      else if (std::fabs(b + bi) <= 1e-12 * sc) { u = v; flip = 1; }
+    }
+    if (u < 0) {
+      if ((int)reps.size() == REP_CHUNK) {
+        flush(j0, j);
+        j0 = j;
+      }
+      u = (int)reps.size();
+      reps.push_back(Rep{j, real});
+    }
+    use_rep[j] = u;
+    use_flip[j] = flip;
   }
+  flush(j0, q);
   {
     int hq[QMAX];
     SKR_HIP(hipMemcpyAsync(hq, info_.p + 2, q * sizeof(int), hipMemcpyDeviceToHost, st_));

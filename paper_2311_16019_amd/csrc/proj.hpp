@@ -8,6 +8,8 @@
 
 #include <string>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace skr {
@@ -68,9 +70,9 @@ class ProjSolver {
   static constexpr int DEFL_NS = 4;
   hipStream_t dst_[DEFL_NS - 2] = {};
   hipEvent_t dev_[DEFL_NS] = {};
-  DBuf<double> kb_[DEFL_NS];
-  DBuf<int> gjw2_[DEFL_NS];
-  DBuf<double> gjd2_[DEFL_NS];
+  std::vector<DBuf<double>> kbv_;  // one eliminated shifted matrix per distinct shift
+  std::vector<DBuf<int>> gjwv_;
+  std::vector<DBuf<double>> gjdv_;
   DBuf<double> gapply_;
   DBuf<int> acaint_;
 };
