@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-tpksm", action="store_true", help="skip the t-PKSM comparison solve")
     ap.add_argument("--concurrent", action="store_true",
                     help="run the forward and the adjoint solve of a step concurrently (two host threads, "
                          "one stream each)")
@@ -318,7 +319,16 @@ def main():
                                 projected=dict(forward=f64.proj, adjoint=a64.proj))
     # Algorithm 2 (t-PKSM: the same block steps with no embedding) on the same forward
     # problem and window, for comparison with s-PKSM
-    prm_t = params(args.precision, profile=True)
+    if not args.no_tpksm:
+        out["tpksm_forward"] = tpksm_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out))
+
+
+def tpksm_leg(skr, torch, A, B, C1, C2, prm_t):
+    """Algorithm 2 (t-PKSM: the same block steps with no embedding) on the same forward
+    problem and window, for comparison with s-PKSM."""
     prm_t["sketch"] = "none"
     skr.solve(A, B, C1, C2, **prm_t)  # warm-up
     torch.cuda.synchronize()
@@ -326,15 +336,10 @@ def main():
     ft = skr.solve(A, B, C1, C2, **prm_t)
     torch.cuda.synchronize()
     elt = time.perf_counter() - t1
-    out["tpksm_forward"] = dict(ms=round(1000.0 * elt, 2), block_steps_per_s=round(ft.iters / elt, 1),
-                                time_split_ms=dict(block_steps=round(ft.ms_steps, 2),
-                                                   projected_solves=round(ft.ms_proj, 2),
-                                                   recovery=round(ft.ms_recover, 2)),
-                                rho_rel=ft.rho_rel, true_residual=skr.true_residual(A, B, ft.X1, ft.X2, C1, C2),
-                                projected=ft.proj)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
-    print(json.dumps(out))
+    return dict(ms=round(1000.0 * elt, 2), block_steps_per_s=round(ft.iters / elt, 1),
+                time_split_ms=dict(block_steps=round(ft.ms_steps, 2), projected_solves=round(ft.ms_proj, 2),
+                                   recovery=round(ft.ms_recover, 2)),
+                rho_rel=ft.rho_rel, true_residual=skr.true_residual(A, B, ft.X1, ft.X2, C1, C2), projected=ft.proj)
 
 
 if __name__ == "__main__":

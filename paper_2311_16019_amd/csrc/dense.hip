@@ -447,21 +447,45 @@ __global__ void __launch_bounds__(BG_T) basis_mfma_kernel(int n, int r, int K, i
 #pragma unroll
     for (int b = 0; b < NCS; ++b) acc[a][b] = bg_d4{0.0, 0.0, 0.0, 0.0};
 
+  // The next chunk's W entries and A values are loaded into registers while the current
+  // chunk is multiplied, so neither HBM (A) nor L2 (W) latency stalls the matrix cores.
+  constexpr int TG = BG_KC / 16;                           // 16-wide q groups per chunk
+  constexpr int WPT = (NCS * 16 * BG_KC + BG_T - 1) / BG_T;  // staged W entries per thread
+  double wreg[WPT], anext[TG][BG_RS][4];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + BG_T * u;
+      const int cc = e / BG_KC, kk = e - cc * BG_KC;
+      const int q = q0 + kk;
+      wreg[u] = (e < NCS * 16 * BG_KC && cc < ncol && q < K) ? W[q + (size_t)(col0 + cc) * ldw] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < TG; ++t)
+#pragma unroll
+      for (int rs = 0; rs < BG_RS; ++rs)
+        bg_load_a<T, VEC>(U, n, r, K, row0 + rs * 16 + jl, q0 + 16 * t + 4 * g, anext[t][rs]);
+  };
+  fetch(0);
   for (int q0 = 0; q0 < K; q0 += BG_KC) {
     // stage W(q0 : q0 + KC, col0 : col0 + 16 NCS) with q fastest; zeros outside
     __syncthreads();
-    for (int e = tid; e < NCS * 16 * BG_KC; e += BG_T) {
-      const int cc = e / BG_KC, kk = e - cc * BG_KC;
-      const int q = q0 + kk;
-      Ws[cc * BG_LDW + kk] = (cc < ncol && q < K) ? W[q + (size_t)(col0 + cc) * ldw] : 0.0;
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + BG_T * u;
+      if (e < NCS * 16 * BG_KC) Ws[(e / BG_KC) * BG_LDW + e % BG_KC] = wreg[u];
     }
     __syncthreads();
+    double a[TG][BG_RS][4];
 #pragma unroll
-    for (int t = 0; t < BG_KC / 16; ++t) {
-      const int qg = q0 + 16 * t + 4 * g;  // this lane group's four q values: qg .. qg + 3
-      double a[BG_RS][4];
+    for (int t = 0; t < TG; ++t)
 #pragma unroll
-      for (int rs = 0; rs < BG_RS; ++rs) bg_load_a<T, VEC>(U, n, r, K, row0 + rs * 16 + jl, qg, a[rs]);
+      for (int rs = 0; rs < BG_RS; ++rs)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[t][rs][s] = anext[t][rs][s];
+    if (q0 + BG_KC < K) fetch(q0 + BG_KC);
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
 #pragma unroll
       for (int cs = 0; cs < NCS; ++cs) {
         const double* wp = Ws + (cs * 16 + jl) * BG_LDW + 16 * t + 4 * g;
@@ -472,7 +496,7 @@ __global__ void __launch_bounds__(BG_T) basis_mfma_kernel(int n, int r, int K, i
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int rs = 0; rs < BG_RS; ++rs)
-            acc[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rs][s], b[s], acc[rs][cs], 0, 0, 0);
+            acc[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][rs][s], b[s], acc[rs][cs], 0, 0, 0);
       }
     }
   }
