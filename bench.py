@@ -301,8 +301,6 @@ def main():
                             projected=f.proj),
                adjoint=dict(iters=a.iters, rho_rel=a.rho_rel, ell=a.ell, projected=a.proj))
     if not args.no_fp64_compare and args.precision == "mixed":
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
         one_step("fp64", profile=True)  # warm-up: FP64 workspaces differ from the mixed ones
         torch.cuda.synchronize()
         t1 = time.perf_counter()
