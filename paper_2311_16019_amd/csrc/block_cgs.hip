@@ -88,15 +88,27 @@ __device__ inline void write_partials(const double (&acc)[NV], double* part, int
 // ------------------------------------------------------------------------- pass 1
 // 1a: U~ = (Op U'_d) P_d (or the start block), stored in T.  Few registers, so many
 // wavefronts per CU hide the dependent row-pointer -> column -> gather loads.
+// Nonzeros of a row whose loads are in flight together: five covers the 2D stencils in one
+// batch and keeps the kernel at six wavefronts per SIMD.
+constexpr int SPMM_UN = 5;
+
 template <typename T, int R>
 __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> s1) {
   constexpr int RR = R * R;
   const Rows wi = rows_of(s0, s1);
   const CgsPass<T>& sp = wi.space ? s1 : s0;
   __shared__ double pd[RR];
-  for (int i = threadIdx.x; i < RR; i += WG) pd[i] = sp.Pd ? sp.Pd[i] : ((i / R == i % R) ? 1.0 : 0.0);
-  __syncthreads();
+  // slice offsets of this workgroup's rows, loaded once instead of per row
+  constexpr int MAXSL = 64;
+  __shared__ int soff[MAXSL + 1];
   const CsrView<T> A = sp.A;
+  const int q0 = wi.row0 / SELL_C;
+  const int nsl = (wi.row1 - wi.row0 + SELL_C - 1) / SELL_C;
+  const bool pre = A.sell_off && nsl <= MAXSL;
+  for (int i = threadIdx.x; i < RR; i += WG) pd[i] = sp.Pd ? sp.Pd[i] : ((i / R == i % R) ? 1.0 : 0.0);
+  if (pre)
+    for (int i = threadIdx.x; i <= nsl; i += WG) soff[i] = A.sell_off[q0 + i];
+  __syncthreads();
   for (int base = wi.row0; base < wi.row1; base += WG) {
     const int row = base + threadIdx.x;
     if (row >= wi.row1) continue;
@@ -112,18 +124,19 @@ __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> 
         // sliced ELL: a wavefront's 64 rows are one slice, so each index load (and each FP32
         // value load) of the wavefront is one contiguous 256-byte access
         const int q = row / SELL_C, l = row % SELL_C;
-        const int e0 = A.sell_off[q], w = (A.sell_off[q + 1] - e0) / SELL_C;
-        for (int jb = 0; jb < w; jb += 8) {
-          int cols[8];
-          double vv[8];
+        const int e0 = pre ? soff[q - q0] : A.sell_off[q];
+        const int w = ((pre ? soff[q - q0 + 1] : A.sell_off[q + 1]) - e0) / SELL_C;
+        for (int jb = 0; jb < w; jb += SPMM_UN) {
+          int cols[SPMM_UN];
+          double vv[SPMM_UN];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
+          for (int j = 0; j < SPMM_UN; ++j) {
             const bool ok = jb + j < w;
             cols[j] = ok ? A.sell_col[e0 + (jb + j) * SELL_C + l] : row;
             vv[j] = ok ? static_cast<double>(A.sell_val[e0 + (jb + j) * SELL_C + l]) : 0.0;
           }
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
+          for (int j = 0; j < SPMM_UN; ++j) {
             if (jb + j < w) {
               double x[R];
               load_row<T, R>(sp.X, cols[j], x);
@@ -134,18 +147,18 @@ __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> 
         }
       } else {
       const int k0 = A.rowptr[row], k1 = A.rowptr[row + 1];
-      // up to 8 nonzeros at a time: their indices and values, then their gathers, in flight
-      for (int kb = k0; kb < k1; kb += 8) {
-        int cols[8];
-        double vv[8];
+      // SPMM_UN nonzeros at a time: their indices and values, then their gathers, in flight
+      for (int kb = k0; kb < k1; kb += SPMM_UN) {
+        int cols[SPMM_UN];
+        double vv[SPMM_UN];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < SPMM_UN; ++j) {
           const bool ok = kb + j < k1;
           cols[j] = ok ? A.colind[kb + j] : row;
           vv[j] = ok ? static_cast<double>(A.val[kb + j]) : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < SPMM_UN; ++j) {
           if (kb + j < k1) {
             double x[R];
             load_row<T, R>(sp.X, cols[j], x);
@@ -464,10 +477,10 @@ __global__ void __launch_bounds__(RED_T) cgs_reduce2_kernel(CgsSmall s0, CgsSmal
 // Workgroups of the SpMM sweep: about four rows per thread, so that many wavefronts per CU
 // hide the dependent loads (the other sweeps use the fewer workgroups of CgsPass::nwg,
 // whose partials the reductions read).
-inline int spmm_wgs(int n) {
-  int g = ceil_div(n, 4 * WG);
+inline int spmm_wgs(int n) {  // two rows per thread: short latency chains, a small tail
+  int g = ceil_div(n, 2 * WG);
   g = (g + 7) / 8 * 8;
-  return std::max(8, std::min(2048, g));
+  return std::max(8, std::min(8192, g));
 }
 
 template <typename T, int R, int NW>
