@@ -143,6 +143,18 @@ SKR_API int skr_solve(skr_op A, skr_op B, const double* C1, const double* C2, in
 SKR_API int skr_adjoint_solve(skr_op A, skr_op B, const double* G1, const double* G2, int64_t r,
                       const skr_params* params, void* stream, skr_result* out);
 
+/*
+ * Lyapunov specialisation (the paper's Sec. 4 setting): A X + X A^T = C C^T.  With B = A^T
+ * and C2 = C1 = C the second Krylov space K(B^T, C2) of Algorithm 1 is K(A, C) itself; the
+ * solve builds it once, with one embedding S_U (seed as above), so M_B = M_A and each block
+ * step and each sign-iteration step does half of the tandem work.  Same parameters as
+ * skr_solve (sketch sparse sign or none); requires r <= 4, k <= 3 and stored-basis recovery
+ * (SKR_ENOTSUP otherwise).  The result holds factors of the symmetric X ~ X1 X2^T (both
+ * n x ell; X1 and X2 themselves differ).  C: device FP64 n x r row-major.
+ */
+SKR_API int skr_lyap_solve(skr_op A, const double* C, int64_t r, const skr_params* params, void* stream,
+                           skr_result* out);
+
 /* Scalars of a result: rank ell of the factors, block steps d, last relative residual
  * estimate rho/||beta_1 beta_2^T||_F, and the status returned by the solve. */
 SKR_API int skr_result_info(skr_result res, int64_t* ell, int32_t* iters, double* rho_rel, int32_t* status);

@@ -203,6 +203,22 @@ def adjoint_solve(A: Operator, B: Operator, G1, G2, stream=None, **params) -> Re
     return _run("skr_adjoint_solve", A, B, G1, G2, stream, **params)
 
 
+def lyap_solve(A: Operator, C, stream=None, **params) -> Result:
+    """Solve the Lyapunov equation ``A X + X A^T = C C^T`` on one Krylov space (the
+    specialisation of Algorithm 1 with ``B = A^T``, ``C2 = C1``); ``X ~ X1 X2^T`` is
+    symmetric.  Same ``params`` as :func:`solve` (two-pass block step and stored basis)."""
+    lib = _lib.load()
+    r = C.shape[1]
+    pc = _dev_ptr(C, "C", (A.n, r))
+    prm = _params(**params)
+    h = ctypes.c_void_p()
+    _lib.check(lib.skr_lyap_solve(A._h, pc, r, ctypes.byref(prm), _stream(stream), ctypes.byref(h)))
+    try:
+        return _collect(h, A.n, A.n, stream)
+    finally:
+        lib.skr_result_destroy(h)
+
+
 def true_residual(A: Operator, B: Operator, X1, X2, C1, C2, stream=None) -> float:
     """``||A X + X B - C1 C2^T||_F / ||C1 C2^T||_F`` for ``X = X1 X2^T`` (on the GPU)."""
     lib = _lib.load()

@@ -249,6 +249,18 @@ int skr_adjoint_solve(skr_op A, skr_op B, const double* G1, const double* G2, in
   });
 }
 
+int skr_lyap_solve(skr_op A, const double* C, int64_t r, const skr_params* params, void* stream, skr_result* out) {
+  return guarded([&] {
+    SKR_REQUIRE(out && params, "null argument");
+    check_op(A);
+    SKR_REQUIRE(r >= 1 && r <= RMAX, "r must be in [1, 16]");
+    *out = nullptr;
+    skr_result_s* res = run_solve(A, 0, nullptr, 0, C, C, (int)r, *params, as_stream(stream));
+    *out = res;
+    return (int)res->status;
+  });
+}
+
 int skr_result_info(skr_result res, int64_t* ell, int32_t* iters, double* rho_rel, int32_t* status) {
   return guarded([&] {
     SKR_REQUIRE(res, "null result");

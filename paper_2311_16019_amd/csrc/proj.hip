@@ -30,6 +30,10 @@ constexpr double NS_SWITCH = 5e-3;
 
 enum Scal { LDA = 0, LDB, MU, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RHO2B, RES2, F2, YN2, SCAL_N };
 
+__global__ void copy_scalar_kernel(const double* src, double* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 __global__ void set_scalar_kernel(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -670,28 +674,41 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
     if (!schulz) {
       // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
-      dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
-      dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
-      dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
+      if (!lyap_) {
+        dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
+        dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
+        dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
+      }
       SKR_HIP(hipEventRecord(ev_aux_, aux_));
       dense::copy(m, m, a_.p, m, lu_.p, m, st_);
       dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, s + LDA, st_);
       dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
       SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
+      if (lyap_) {  // B_k = A_k^T: B_k^{-1} = (A_k^{-1})^T, log|det B_k| = log|det A_k|
+        dense::transpose(m, m, ai_.p, m, bi_.p, m, st_);
+        hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, st_, s + LDA, s + LDB);
+        check_launch("copy_scalar");
+      }
       hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
       check_launch("mu");
       dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
       dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, st_);
     } else {
       // B^2 -> lub_, B^{-1} ~ 2B - B B^2 -> bi_ on the auxiliary stream
-      dense::gemm(false, false, m, m, m, 1.0, b_.p, m, b_.p, m, 0.0, lub_.p, m, aux_);
-      dense::copy(m, m, b_.p, m, bi_.p, m, aux_);
-      dense::gemm(false, false, m, m, m, -1.0, b_.p, m, lub_.p, m, 2.0, bi_.p, m, aux_);
+      if (!lyap_) {
+        dense::gemm(false, false, m, m, m, 1.0, b_.p, m, b_.p, m, 0.0, lub_.p, m, aux_);
+        dense::copy(m, m, b_.p, m, bi_.p, m, aux_);
+        dense::gemm(false, false, m, m, m, -1.0, b_.p, m, lub_.p, m, 2.0, bi_.p, m, aux_);
+      }
       SKR_HIP(hipEventRecord(ev_aux_, aux_));
       // A^2 -> lu_, A^{-1} ~ 2A - A A^2 -> ai_
       dense::gemm(false, false, m, m, m, 1.0, a_.p, m, a_.p, m, 0.0, lu_.p, m, st_);
       dense::copy(m, m, a_.p, m, ai_.p, m, st_);
       dense::gemm(false, false, m, m, m, -1.0, a_.p, m, lu_.p, m, 2.0, ai_.p, m, st_);
+      if (lyap_) {  // B = A^T: B^2 = (A^2)^T and the approximate inverse transposes too
+        dense::transpose(m, m, lu_.p, m, lub_.p, m, st_);
+        dense::transpose(m, m, ai_.p, m, bi_.p, m, st_);
+      }
       // w2 = 2C + (AC)B - A(AC) - C B^2, the (1,2) block of Z (2I - Z^2)
       dense::gemm(false, false, m, m, m, 1.0, a_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
       dense::copy(m, m, c_.p, m, w2_.p, m, st_);
@@ -708,7 +725,7 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     SKR_HIP(hipMemcpyAsync(hs.data(), s, SCAL_N * sizeof(double), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipMemcpyAsync(hinfo, info_.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipStreamSynchronize(st_));
-    if (hinfo[0] || hinfo[1])
+    if (hinfo[0] || (!lyap_ && hinfo[1]))  // the Lyapunov solve does not invert B
       throw Error(SKR_EPROJ, "projected matrix singular during the sign iteration (d = " + std::to_string(d) + ")");
     const double rel = std::sqrt(std::max(hs[DA] / hs[NA], hs[DB] / hs[NB_]));
     if (!std::isfinite(rel))

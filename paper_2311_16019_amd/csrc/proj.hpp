@@ -44,6 +44,9 @@ class ProjSolver {
   // Residual estimate of the truncated Arnoldi method (Algorithm 2):
   // sqrt(d r) (||Y E_d g^T||_F + ||h E_d^T Y||_F) instead of sqrt of the sum of squares.
   void use_truncated_estimate(bool on) { trunc_est_ = on; }
+  // Lyapunov equation (M_B = M_A): the sign iterates satisfy B_k = A_k^T, so each step
+  // inverts A_k only and transposes.
+  void use_lyapunov(bool on) { lyap_ = on; }
   const double* Y1() const { return y1_.p; }
   const double* Y2() const { return y2_.p; }
   int m() const { return m_; }
@@ -57,6 +60,7 @@ class ProjSolver {
                      const double* F11, int f_trans, int q, double* G);
   int r_, mmax_, m_ = 0;
   bool trunc_est_ = false;
+  bool lyap_ = false;
   hipStream_t st_;
   hipStream_t aux_ = nullptr;  // second stream: the two inversions of a Newton step overlap
   hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr;

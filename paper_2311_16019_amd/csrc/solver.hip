@@ -184,8 +184,11 @@ struct Space {
 template <typename T>
 class Solver {
  public:
+  // B == nullptr: the Lyapunov specialisation A X + X A^T = C1 C1^T (one Krylov space; the
+  // second space is an empty placeholder that the tandem kernels skip).
   Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
       : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
+    lyap_ = (B == nullptr);
     aux_ = stream_acquire();
     SKR_HIP(hipEventCreateWithFlags(&ev_block_, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_sketch_, hipEventDisableTiming));
@@ -213,13 +216,16 @@ class Solver {
     }
     ld_ = (p.maxit + 1) * r;
     fast_ = cgs_supported(r, p.k);
+    if (lyap_ && !fast_) throw Error(SKR_ENOTSUP, "the Lyapunov solve needs the two-pass block step (r <= 4, k <= 3)");
+    if (lyap_ && p.recover != SKR_RECOVER_STORED)
+      throw Error(SKR_ENOTSUP, "the Lyapunov solve needs stored-basis recovery");
     int dev = 0;
     SKR_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     SKR_HIP(hipGetDeviceProperties(&prop, dev));
     lds_limit_ = std::max<size_t>(65536, prop.sharedMemPerBlock);
     setup(sp_[0], A, tu);
-    setup(sp_[1], B, tv);
+    setup(sp_[1], lyap_ ? nullptr : B, tv);
   }
 
   ~Solver() {
@@ -245,7 +251,7 @@ class Solver {
     PoolQuiet quiet;  // entered once all work of this call has completed
     std::unique_ptr<skr_result_s> res(new skr_result_s());
     res->n1 = sp_[0].n;
-    res->n2 = sp_[1].n;
+    res->n2 = lyap_ ? sp_[0].n : sp_[1].n;
     hipEvent_t e0, e1;
     SKR_HIP(hipEventCreate(&e0));
     SKR_HIP(hipEventCreate(&e1));
@@ -258,6 +264,7 @@ class Solver {
     SKR_HIP(hipMemcpyAsync(&hb[0], sp_[0].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipStreamSynchronize(st_));
+    if (lyap_) hb[1] = hb[0];
     if (hb[0] != INT_MAX || hb[1] != INT_MAX)
       throw Error(SKR_EINVAL, "right-hand side factor is rank deficient or its sketch is singular");
     for (int i = 0; i < r_ * r_; ++i) rhs += rhs_block_host_[i] * rhs_block_host_[i];
@@ -266,6 +273,7 @@ class Solver {
 
     ProjSolver proj(r_, p_.maxit * r_, st_);
     proj.use_truncated_estimate(!sketched_);
+    proj.use_lyapunov(lyap_);
     int status = SKR_NOT_CONVERGED, dfinal = 0;
     double rho_rel = 0.0;
     for (int d = 1; d <= p_.maxit; ++d) {
@@ -276,6 +284,7 @@ class Solver {
         SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
         SKR_HIP(hipEventRecord(e1, st_));
         SKR_HIP(hipEventSynchronize(e1));
+        if (lyap_) hb[1] = hb[0];
         float ms = 0.f;
         SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
         res->ms_steps += ms;
@@ -286,7 +295,7 @@ class Solver {
         SKR_REQUIRE(dc >= 1, "breakdown in the first block step");
         SKR_HIP(hipEventRecord(e0, st_));
         ProjSpace pu{sp_[0].H.p, sp_[0].Tm.p, ld_, hb[0] == dc};
-        ProjSpace pv{sp_[1].H.p, sp_[1].Tm.p, ld_, hb[1] == dc};
+        ProjSpace pv = lyap_ ? pu : ProjSpace{sp_[1].H.p, sp_[1].Tm.p, ld_, hb[1] == dc};
         const double rho = proj.solve(dc, pu, pv, F11_.p, &res->last_stats);
         SKR_HIP(hipEventRecord(e1, st_));
         SKR_HIP(hipEventSynchronize(e1));
@@ -309,18 +318,19 @@ class Solver {
     dense::copy(m, ell, proj.Y1(), m, W1.p, m, st_);
     dense::copy(m, ell, proj.Y2(), m, W2.p, m, st_);
     dense::trsm_left_upper(m, ell, sp_[0].Tm.p, ld_, W1.p, m, st_);
-    dense::trsm_left_upper(m, ell, sp_[1].Tm.p, ld_, W2.p, m, st_);
+    Space<T>& sv = lyap_ ? sp_[0] : sp_[1];  // the second space of the factors
+    dense::trsm_left_upper(m, ell, sv.Tm.p, ld_, W2.p, m, st_);
     res->X1.alloc((size_t)sp_[0].n * ell);
-    res->X2.alloc((size_t)sp_[1].n * ell);
+    res->X2.alloc((size_t)sv.n * ell);
     if (p_.recover == SKR_RECOVER_STORED) {
       if (fast_) {  // U_j = U'_j P_j: X = sum_j U'_j (P_j W[j])
         const int g = std::max(1, std::min(4096, ceil_div((int64_t)dfinal * ell, 256)));
         hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sp_[0].Pall.p, W1.p, m);
-        hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sp_[1].Pall.p, W2.p, m);
+        hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sv.Pall.p, W2.p, m);
         check_launch("apply_pending");
       }
       dense::basis_gemm<T>(sp_[0].n, r_, dfinal, ell, 1.0, sp_[0].basis.p, W1.p, m, 0.0, res->X1.p, ell, st_);
-      dense::basis_gemm<T>(sp_[1].n, r_, dfinal, ell, 1.0, sp_[1].basis.p, W2.p, m, 0.0, res->X2.p, ell, st_);
+      dense::basis_gemm<T>(sv.n, r_, dfinal, ell, 1.0, sv.basis.p, W2.p, m, 0.0, res->X2.p, ell, st_);
     } else {
       replay(C1, C2, dfinal, ell, W1.p, W2.p, res->X1.p, res->X2.p);
     }
@@ -339,8 +349,8 @@ class Solver {
 
  private:
   void setup(Space<T>& s, const skr_op_s* op, int t) {
-    s.A = csr_view<T>(op, t);
-    s.n = (int)op->n;
+    s.A = op ? csr_view<T>(op, t) : CsrView<T>{};  // no operator: an empty space (n = 0)
+    s.n = op ? (int)op->n : 0;
     s.rr = r_;
     s.nwg = step_wgs(s.n);
     s.nwg2 = cgs_wgs(s.n);
@@ -489,23 +499,27 @@ class Solver {
         check_launch("unit_diag");
       }
       F11_.alloc((size_t)r_ * r_);
-      hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p, sp_[1].Tm.p,
-                         ld_, sp_[1].ell.p, F11_.p);
+      hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p,
+                         second().Tm.p, ld_, second().ell.p, F11_.p);
       check_launch("rhs_block");
       rhs_block_host_.assign((size_t)r_ * r_, 0.0);
       return;
     }
     const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
     for (int i = 0; i < 2; ++i)
-      launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
+      if (sp_[i].n > 0)  // the Lyapunov solve's empty placeholder space has no table
+        launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
     sketch(1, st_);
     whiten(0, 0, st_);
     F11_.alloc((size_t)r_ * r_);
-    hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p, sp_[1].Tm.p,
-                       ld_, sp_[1].ell.p, F11_.p);
+    hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p,
+                       second().Tm.p, ld_, second().ell.p, F11_.p);
     check_launch("rhs_block");
     rhs_block_host_.assign((size_t)r_ * r_, 0.0);
   }
+
+  // The second space of the equation: the V space, or the U space again for Lyapunov.
+  const Space<T>& second() const { return lyap_ ? sp_[0] : sp_[1]; }
 
   static uint64_t mix64_host(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -706,6 +720,7 @@ class Solver {
   int r_;
   bool fast_ = false;      // two-pass block step (r <= 4, k <= 3)
   bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
+  bool lyap_ = false;      // A X + X A^T = C1 C1^T on one Krylov space
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;
@@ -723,8 +738,9 @@ class Solver {
 
 skr_result_s* run_solve(const skr_op_s* A, int tu, const skr_op_s* B, int tv, const double* C1, const double* C2,
                         int r, const skr_params& p, hipStream_t st) {
-  SKR_REQUIRE(A && B, "null operator");
+  SKR_REQUIRE(A, "null operator");
   SKR_REQUIRE(C1 && C2, "null right-hand side factor");
+  SKR_REQUIRE(B || C1 == C2, "the Lyapunov solve takes one right-hand side factor");
   if (p.precision == SKR_FP64) {
     Solver<double> s(A, tu, B, tv, r, p, st);
     return s.run(C1, C2);

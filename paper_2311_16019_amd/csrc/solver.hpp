@@ -34,6 +34,8 @@ namespace skr {
 
 // Solve with Krylov spaces K(opU, C1) and K(opV, C2) where opU = A (transposed if tu)
 // and opV = B (transposed if tv).  The forward equation uses (A, tu=0) and (B, tv=1).
+// B == nullptr (then C2 == C1): the Lyapunov equation opU X + X opU^T = C1 C1^T on the one
+// space K(opU, C1) (the V space of B = opU^T, C2 = C1 with S_V = S_U is the same space).
 skr_result_s* run_solve(const skr_op_s* A, int tu, const skr_op_s* B, int tv, const double* C1, const double* C2,
                         int r, const skr_params& p, hipStream_t st);
 
