@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-tpksm", action="store_true", help="skip the t-PKSM comparison solve")
+    ap.add_argument("--no-lyapunov", action="store_true", help="skip the Lyapunov comparison solve")
     ap.add_argument("--concurrent", action="store_true",
                     help="run the forward and the adjoint solve of a step concurrently (two host threads, "
                          "one stream each)")
@@ -319,9 +320,27 @@ def main():
     # problem and window, for comparison with s-PKSM
     if not args.no_tpksm:
         out["tpksm_forward"] = tpksm_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True))
+    if not args.no_lyapunov:
+        out["lyapunov_forward"] = lyapunov_leg(skr, torch, A, C1, params(args.precision, profile=True), f)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out))
+
+
+def lyapunov_leg(skr, torch, A, C1, prm, f_sylv):
+    """The Lyapunov specialisation A X + X A^T = C1 C1^T on the same operator and window: one
+    Krylov space instead of two (compare its block-step time with the Sylvester solve's)."""
+    skr.lyap_solve(A, C1, **prm)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fl = skr.lyap_solve(A, C1, **prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    return dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fl.iters / el, 1),
+                time_split_ms=dict(block_steps=round(fl.ms_steps, 2), projected_solves=round(fl.ms_proj, 2),
+                                   recovery=round(fl.ms_recover, 2)),
+                sylvester_forward_block_steps_ms=round(f_sylv.ms_steps, 2), rho_rel=fl.rho_rel,
+                projected=fl.proj)
 
 
 def tpksm_leg(skr, torch, A, B, C1, C2, prm_t):

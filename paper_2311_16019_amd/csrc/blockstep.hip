@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
 // w = (sum over chunks of the partial sketches) P / sqrt(zeta), P (r x r row-major) the
 // block's pending right factor or null for the identity.  Each thread sums one entry's
 // chunks (all loads in flight), then the rows of the workgroup are multiplied by P in LDS.
-constexpr int SK_CHMAX = 16;  // sketch_chunks() never exceeds this
+constexpr int SK_CHMAX = 32;  // sketch_chunks() never exceeds this
 template <typename T>
 __global__ void __launch_bounds__(256) sketch_reduce_kernel(SketchSpace<T> a0, SketchSpace<T> a1, const double* P0,
                                                             const double* P1, int s, int r, double scale) {
@@ -515,7 +515,11 @@ int grid_of(const SpaceStep<T>& a, const SpaceStep<T>& b) {
 
 }  // namespace
 
-int sketch_chunks(int n) { return std::max(1, std::min(16, ceil_div(n, 4 * SK_WG))); }
+// Row chunks per space: one workgroup per (chunk, copy); a single space (the Lyapunov
+// solve) takes twice as many so that the launch still fills the GPU.
+int sketch_chunks(int n, int nspaces) {
+  return std::max(1, std::min(nspaces == 1 ? 32 : 16, ceil_div(n, 4 * SK_WG)));
+}
 
 #define SKR_DISPATCH_R(r, ...)                                             \
   switch (r) {                                                             \

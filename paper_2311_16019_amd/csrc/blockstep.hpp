@@ -70,7 +70,7 @@ template <typename T>
 void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b,
                    size_t lds_limit, hipStream_t st);
 
-int sketch_chunks(int n);
+int sketch_chunks(int n, int nspaces);
 // Sketch with a pending right factor: w = (S U') P / sqrt(zeta), P (r x r row-major, device)
 // or null for the identity.
 template <typename T>

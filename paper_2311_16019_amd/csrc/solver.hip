@@ -375,7 +375,7 @@ class Solver {
       s.cgs.zero(st_);
     }
     s.broken.alloc(1);
-    s.nchunk = sketch_chunks(s.n);
+    s.nchunk = sketch_chunks(s.n, lyap_ ? 1 : 2);
     s.skpart.alloc((size_t)s.nchunk * s_ * r_);
     s.w.alloc((size_t)s_ * r_);
     s.c1.alloc((size_t)ld_ * r_);
@@ -538,7 +538,7 @@ class Solver {
   void whiten(int d, int step, hipStream_t s) {
     WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].w.p, sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p, sp_[0].broken.p, ld_};
     WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].w.p, sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p, sp_[1].broken.p, ld_};
-    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s);
+    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s, lyap_ ? 1 : 2);
   }
 
   // Two-pass block step (r <= 4, k <= 3): pass 1 + reduce 1, pass 2 + reduce 2.

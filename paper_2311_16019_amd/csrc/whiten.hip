@@ -409,32 +409,34 @@ size_t whiten_part_doubles(int s, int r, int maxm) { return (size_t)ceil_div(s, 
     default: throw Error(SKR_ENOTSUP, "block size r must be in [1, 16]");  \
   }
 
-void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, hipStream_t st) {
+void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, hipStream_t st,
+                   int nspaces) {
+  const int ns = nspaces == 1 ? 1 : 2;  // grid extent over the spaces: b is skipped when 1
   if (m > 0) {
     const int nchunk = ceil_div(s, QT_ROWS);
     for (int pass = 0; pass < 2; ++pass) {
       WH_DISPATCH(r, {
         const int tile = (WT / 64) * qt_cols<RR_>();
-        hipLaunchKernelGGL((qtw_split_kernel<RR_>), dim3(ceil_div(m, tile), nchunk, 2), dim3(WT), 0, st, a, b, s, m);
+        hipLaunchKernelGGL((qtw_split_kernel<RR_>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
       });
       check_launch("whiten_qtw");
-      hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * r, 256)), 2), dim3(256), 0, st, a,
+      hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * r, 256)), ns), dim3(256), 0, st, a,
                          b, m, r, nchunk, pass);
       check_launch("whiten_qtw_sum");
-      WH_DISPATCH(r, hipLaunchKernelGGL((qc_rows_kernel<RR_>), dim3(ceil_div(s, QC_ROWS), 2), dim3(WT), 0, st, a, b, s,
+      WH_DISPATCH(r, hipLaunchKernelGGL((qc_rows_kernel<RR_>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s,
                                         m, pass));
       check_launch("whiten_qc");
     }
   }
   if (r <= 4 && s <= FIN_RPT * FIN_T) {
     switch (r) {
-      case 1: hipLaunchKernelGGL((whiten_finish_reg_kernel<1>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
-      case 2: hipLaunchKernelGGL((whiten_finish_reg_kernel<2>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
-      case 3: hipLaunchKernelGGL((whiten_finish_reg_kernel<3>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
-      default: hipLaunchKernelGGL((whiten_finish_reg_kernel<4>), dim3(2), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 1: hipLaunchKernelGGL((whiten_finish_reg_kernel<1>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 2: hipLaunchKernelGGL((whiten_finish_reg_kernel<2>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 3: hipLaunchKernelGGL((whiten_finish_reg_kernel<3>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      default: hipLaunchKernelGGL((whiten_finish_reg_kernel<4>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
     }
   } else {
-    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(2), dim3(FT), 0, st, a, b, s, m, step));
+    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(ns), dim3(FT), 0, st, a, b, s, m, step));
   }
   check_launch("whiten_finish");
 }

@@ -22,7 +22,9 @@ struct WhitenSpace {
 size_t whiten_part_doubles(int s, int r, int maxm);
 
 // Append the block for step d (m = d r current columns of Q).  `init` = true builds Q_1,
-// T_1 from w alone (m = 0).  Processes both spaces in every launch.
-void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, hipStream_t st);
+// T_1 from w alone (m = 0).  Processes both spaces in every launch, or only `a` when
+// nspaces is 1.
+void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, hipStream_t st,
+                   int nspaces = 2);
 
 }  // namespace skr
