@@ -170,10 +170,13 @@ struct Space {
   int nslots = 0;
   bool stored = true;
   DBuf<T> basis, work;
-  DBuf<double> H, Tm, Q, small, part, skpart, w, c1, c2, wpart, ell;
+  DBuf<double> H, Tm, Q, small, part, skpart, w, w2, c1, c2, wpart, ell;
   DBuf<double> Pall, Gall, Xall, cgs;  // two-pass step: pending factors, Gram blocks, state
   DBuf<int> broken;
   DBuf<uint16_t> tab;
+  // sketch of block j: two buffers by parity, so that the sketch of block j + 1 can be
+  // written while block j's whitening still reads its own
+  double* wbuf(int j) const { return (j & 1) ? w2.p : w.p; }
   T* slot(int j) const {  // 1-based basis block j
     const int idx = stored ? (j - 1) : ((j - 1) % nslots);
     return basis.p + (size_t)idx * n * rr;
@@ -190,6 +193,8 @@ class Solver {
       : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
     lyap_ = (B == nullptr);
     aux_ = stream_acquire();
+    aux2_ = stream_acquire();
+    for (auto& e : ev_whiten_) SKR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_block_, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_sketch_, hipEventDisableTiming));
     SKR_HIP(hipEventCreateWithFlags(&ev_aux_done_, hipEventDisableTiming));
@@ -230,20 +235,24 @@ class Solver {
 
   ~Solver() {
     if (aux_) (void)hipStreamSynchronize(aux_);
+    if (aux2_) (void)hipStreamSynchronize(aux2_);
     (void)hipStreamSynchronize(st_);
     quiet_.enter();  // every buffer below is idle now
     if (ev_block_) (void)hipEventDestroy(ev_block_);
     if (ev_sketch_) (void)hipEventDestroy(ev_sketch_);
     if (ev_aux_done_) (void)hipEventDestroy(ev_aux_done_);
+    for (auto e : ev_whiten_)
+      if (e) (void)hipEventDestroy(e);
     if (aux_) stream_release(aux_);
+    if (aux2_) stream_release(aux2_);
   }
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;
 
   // The sketch and the sketched QR update of step d run on the auxiliary stream; the
   // solve's stream waits for them before anything reads T, Q or the breakdown flags.
-  void join_aux() {
-    SKR_HIP(hipEventRecord(ev_aux_done_, aux_));
+  void join_aux() {  // the whitening stream's last work follows the last sketch
+    SKR_HIP(hipEventRecord(ev_aux_done_, aux2_));
     SKR_HIP(hipStreamWaitEvent(st_, ev_aux_done_, 0));
   }
 
@@ -378,6 +387,7 @@ class Solver {
     s.nchunk = sketch_chunks(s.n, lyap_ ? 1 : 2);
     s.skpart.alloc((size_t)s.nchunk * s_ * r_);
     s.w.alloc((size_t)s_ * r_);
+    s.w2.alloc((size_t)s_ * r_);
     s.c1.alloc((size_t)ld_ * r_);
     s.c2.alloc((size_t)ld_ * r_);
     s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
@@ -528,16 +538,19 @@ class Solver {
   }
 
   void sketch(int j, hipStream_t s) {
-    SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].w.p, sp_[0].n, sp_[0].nchunk};
-    SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].w.p, sp_[1].n, sp_[1].nchunk};
+    SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].wbuf(j), sp_[0].n, sp_[0].nchunk};
+    SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].wbuf(j), sp_[1].n, sp_[1].nchunk};
     const size_t off = (size_t)j * r_ * r_;
     launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, fast_ ? sp_[0].Pall.p + off : nullptr,
                              fast_ ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
   }
 
   void whiten(int d, int step, hipStream_t s) {
-    WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].w.p, sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p, sp_[0].broken.p, ld_};
-    WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].w.p, sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p, sp_[1].broken.p, ld_};
+    // appends block d + 1, whose sketch is in wbuf(d + 1)
+    WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].wbuf(d + 1), sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p,
+                   sp_[0].broken.p, ld_};
+    WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].wbuf(d + 1), sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p,
+                   sp_[1].broken.p, ld_};
     launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s, lyap_ ? 1 : 2);
   }
 
@@ -570,18 +583,23 @@ class Solver {
     after_step(d);
   }
 
-  // U_{d+1} is final: sketch it and update Q, T concurrently with the next block step.
+  // U_{d+1} is final: sketch it (stream aux_) and update Q, T (stream aux2_) concurrently
+  // with the next block step; the sketch of block d + 2 overlaps this whitening.
   void after_step(int d) {
     if (!sketched_) return;  // t-PKSM: no embedding
     SKR_HIP(hipEventRecord(ev_block_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
+    // the whitening of block d - 1 read the buffer that the sketch of block d + 1 writes
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_whiten_[(d + 1) & 1], 0));
     prof_.begin(KF_SKETCH, aux_);
     sketch(d + 1, aux_);
     prof_.end();
     SKR_HIP(hipEventRecord(ev_sketch_, aux_));
-    prof_.begin(KF_WHITEN, aux_);
-    whiten(d, d, aux_);
+    SKR_HIP(hipStreamWaitEvent(aux2_, ev_sketch_, 0));
+    prof_.begin(KF_WHITEN, aux2_);
+    whiten(d, d, aux2_);
     prof_.end();
+    SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 1], aux2_));
   }
 
   void block_step(int d) {
@@ -728,8 +746,10 @@ class Solver {
   size_t lds_limit_ = 65536;
   Space<T> sp_[2];
   Profiler prof_;
-  hipStream_t aux_ = nullptr;
+  hipStream_t aux_ = nullptr;   // sketches
+  hipStream_t aux2_ = nullptr;  // sketched QR updates (whitening)
   hipEvent_t ev_block_ = nullptr, ev_sketch_ = nullptr, ev_aux_done_ = nullptr;
+  hipEvent_t ev_whiten_[2] = {nullptr, nullptr};  // last whitening that read wbuf of each parity
   DBuf<double> F11_;
   std::vector<double> rhs_block_host_;
 };
