@@ -383,12 +383,22 @@ int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, in
 
 namespace {
 
-// out_i = -sum_b Z[i][b] X[i][b], Z, X row-major n x l
+// out_i = -sum_b Z[i][b] X[i][b], Z, X row-major n x l.  Sixteen lanes (one DPP row) per
+// matrix row, each striding over the row's columns, so that a row's loads are contiguous;
+// the lanes' sums are combined by DPP butterflies.
 __global__ void rowdot_kernel(int n, int l, const double* Z, const double* X, double* out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const int lane16 = threadIdx.x % 16;
+  const int rows_per_block = blockDim.x / 16;
+  for (int i0 = blockIdx.x * rows_per_block; i0 < n; i0 += gridDim.x * rows_per_block) {
+    const int i = i0 + threadIdx.x / 16;  // rows beyond n take part in the butterflies only
     double s = 0.0;
-    for (int b = 0; b < l; ++b) s += Z[(size_t)i * l + b] * X[(size_t)i * l + b];
-    out[i] = -s;
+    if (i < n)
+      for (int b = lane16; b < l; b += 16) s += Z[(size_t)i * l + b] * X[(size_t)i * l + b];
+    s += dpp_move<0xB1>(s);   // quad_perm [1,0,3,2]
+    s += dpp_move<0x4E>(s);   // quad_perm [2,3,0,1]
+    s += dpp_move<0x124>(s);  // row_ror:4
+    s += dpp_move<0x128>(s);  // row_ror:8
+    if (i < n && lane16 == 0) out[i] = -s;
   }
 }
 
@@ -463,7 +473,7 @@ extern "C" int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q, c
         Z.alloc((size_t)N1 * LX);
         inner(N2, LL, LX, L2, X2, ss.p, st);
         outer(N1, LL, LX, L1, ss.p, Z.p, st);
-        hipLaunchKernelGGL(rowdot_kernel, dim3(std::min(4096, ceil_div(N1, 256))), dim3(256), 0, st, N1, LX, Z.p, X1,
+        hipLaunchKernelGGL(rowdot_kernel, dim3(std::min(8192, ceil_div(N1, 16))), dim3(256), 0, st, N1, LX, Z.p, X1,
                            dsig);
         check_launch("rowdot");
       }

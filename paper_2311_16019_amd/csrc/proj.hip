@@ -2,7 +2,7 @@
 //
 // The small equation M_A Y + Y M_B^T = F is solved with the coupled Newton iteration for
 // the matrix sign function of Z = [[M_A, F], [0, -M_B^T]]: with A_0 = M_A, B_0 = M_B^T,
-// C_0 = F and a scaling mu_k,
+// C_0 = F and a scaling mu_k (Frobenius-norm scaling),
 //     A_{k+1} = (mu A_k + A_k^{-1}/mu)/2,  B_{k+1} = (mu B_k + B_k^{-1}/mu)/2,
 //     C_{k+1} = (mu C_k + A_k^{-1} C_k B_k^{-1}/mu)/2,
 // A_k -> sign(M_A), B_k -> sign(M_B^T) and C_k -> 2 Y when both sign limits are the
@@ -28,19 +28,17 @@ namespace {
 // (Newton-Schulz); scaling is off by then (it stops below 1e-2).
 constexpr double NS_SWITCH = 5e-3;
 
-enum Scal { LDA = 0, LDB, MU, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RHO2B, RES2, F2, YN2, SCAL_N };
-
-__global__ void copy_scalar_kernel(const double* src, double* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
-}
+enum Scal { MU = 0, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RHO2B, RES2, F2, YN2, AI2, BI2, A2, B2, SCAL_N };
 
 __global__ void set_scalar_kernel(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-__global__ void mu_kernel(double* s, int m, int scale) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    s[MU] = scale ? exp(-(s[LDA] + s[LDB]) / (2.0 * m)) : 1.0;
+// Frobenius-norm scaling of the sign iteration, mu = (||Z^{-1}||_F / ||Z||_F)^(1/2) with the
+// diagonal blocks of Z = [[A, C], [0, -B]] standing in for Z (the coupling block C does not
+// enter the spectrum); mu = 1 once the iteration is in its quadratic phase.
+__global__ void mu_kernel(double* s, int scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) s[MU] = scale ? pow((s[AI2] + s[BI2]) / (s[A2] + s[B2]), 0.25) : 1.0;
 }
 
 // F: zero except its top-left r x r block = F11 (row-major) ; column-major m x m
@@ -676,20 +674,22 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
       if (!lyap_) {
         dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
-        dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, s + LDB, aux_);
+        dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, nullptr, aux_);
         dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
       }
       SKR_HIP(hipEventRecord(ev_aux_, aux_));
       dense::copy(m, m, a_.p, m, lu_.p, m, st_);
-      dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, s + LDA, st_);
+      dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, nullptr, st_);
       dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
       SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
-      if (lyap_) {  // B_k = A_k^T: B_k^{-1} = (A_k^{-1})^T, log|det B_k| = log|det A_k|
-        dense::transpose(m, m, ai_.p, m, bi_.p, m, st_);
-        hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, st_, s + LDA, s + LDB);
-        check_launch("copy_scalar");
+      if (lyap_) dense::transpose(m, m, ai_.p, m, bi_.p, m, st_);  // B_k = A_k^T
+      if (scale) {
+        dense::fro2(m, m, ai_.p, m, s + AI2, scratch_.p, st_);
+        dense::fro2(m, m, bi_.p, m, s + BI2, scratch_.p, st_);
+        dense::fro2(m, m, a_.p, m, s + A2, scratch_.p, st_);
+        dense::fro2(m, m, b_.p, m, s + B2, scratch_.p, st_);
       }
-      hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, m, scale ? 1 : 0);
+      hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, scale ? 1 : 0);
       check_launch("mu");
       dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
       dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, st_);
