@@ -86,10 +86,16 @@ class Space:
     ell: np.ndarray = None     # R factor of the start block
     beta: np.ndarray = None    # R factor of S C
     broken: bool = False
+    orth: str = "euclidean"    # 'euclidean' (Algorithm 1) or 'sketched' (inner products of S x)
+    sblocks: dict = field(default_factory=dict)  # j -> S U_j (orth = 'sketched')
 
     def init(self, C: np.ndarray) -> None:
         r, m1 = self.r, (self.maxit + 1) * self.r
-        U1, self.ell = qr_pos(C)
+        if self.orth == "sketched":  # U_1 ell = C with S U_1 orthonormal: ell = R factor of S C
+            _, self.ell = qr_pos(self.S @ C)
+            U1 = sla.solve_triangular(self.ell.T, C.T, lower=True).T
+        else:
+            U1, self.ell = qr_pos(C)
         W = self.S @ U1
         s = W.shape[0]
         self.H = np.zeros((m1, self.maxit * r))
@@ -100,9 +106,13 @@ class Space:
         self.T[:r, :r] = t
         self.beta = t @ self.ell
         self.blocks[1] = U1
+        self.sblocks[1] = W
 
     def step(self, d: int) -> None:
         """Block step ``d``: SpMM, truncated MGS, thin QR, sketched QR update."""
+        if self.orth == "sketched":
+            self.step_sketched(d)
+            return
         r = self.r
         Ut = self.op(self.blocks[d])
         nrm_op = np.linalg.norm(Ut)
@@ -137,6 +147,56 @@ class Space:
             for j in list(self.blocks):
                 if j < d + 2 - self.k:
                     del self.blocks[j]
+
+    def step_sketched(self, d: int) -> None:
+        """Block step ``d`` with the sketched inner product <x, y>_S = (S x)^T (S y) in the
+        truncated Gram-Schmidt and in the thin QR (the variant the paper's appendix A
+        mentions): ``S U~`` is formed once and updated linearly in the sketch space, the
+        orthogonalisation coefficients and the QR factor come from it, and ``U~`` itself is
+        updated once with all coefficients; then ``S U_{d+1} = (S U~) R^{-1}`` feeds the
+        sketched QR update of Prop. 2.1 as before."""
+        r = self.r
+        Ut = self.op(self.blocks[d])
+        SUt = self.S @ Ut
+        nrm_op = np.linalg.norm(SUt)
+        coef = []
+        for i in range(max(1, d - self.k + 1), d + 1):
+            h = self.sblocks[i].T @ SUt
+            SUt = SUt - self.sblocks[i] @ h
+            self.H[(i - 1) * r:i * r, (d - 1) * r:d * r] = h
+            coef.append((i, h))
+        for i, h in coef:
+            Ut = Ut - self.blocks[i] @ h
+        _, hsub = qr_pos(SUt)  # R factor in the sketched norm
+        dg = np.abs(np.diag(hsub))
+        if (np.linalg.norm(SUt) < BREAKDOWN_REL_NORM * nrm_op
+                or dg.min() < BREAKDOWN_REL_DIAG * max(np.abs(hsub).max(), np.finfo(float).tiny)):
+            self.broken = True
+            hsub = np.zeros((r, r))
+            Unew = np.zeros_like(Ut)
+            w = np.zeros_like(SUt)
+            TH, tau, q = np.zeros((d * r, r)), np.eye(r), np.zeros((self.Q.shape[0], r))
+        else:
+            Unew = sla.solve_triangular(hsub.T, Ut.T, lower=True).T    # U~ R^{-1}
+            w = sla.solve_triangular(hsub.T, SUt.T, lower=True).T      # S U_{d+1}
+            Qd = self.Q[:, :d * r]
+            c1 = Qd.T @ w
+            w2 = w - Qd @ c1
+            c2 = Qd.T @ w2
+            w2 = w2 - Qd @ c2
+            q, tau = qr_pos(w2)
+            TH = c1 + c2
+        self.H[d * r:(d + 1) * r, (d - 1) * r:d * r] = hsub
+        self.T[:d * r, d * r:(d + 1) * r] = TH
+        self.T[d * r:(d + 1) * r, d * r:(d + 1) * r] = tau
+        self.Q[:, d * r:(d + 1) * r] = q
+        self.blocks[d + 1] = Unew
+        self.sblocks[d + 1] = w
+        for store in (self.blocks, self.sblocks):
+            if store is self.sblocks or not self.keep_all:
+                for j in list(store):
+                    if j < d + 2 - self.k:
+                        del store[j]
 
     def projected(self, d: int) -> tuple[np.ndarray, np.ndarray]:
         """``M = T_{d+1} H_d_bar T_d^{-1}``: top ``dr`` rows and the last block row's last block."""
@@ -180,8 +240,12 @@ class Result:
 def spksm(A, B, C1, C2, *, k: int, maxit: int, tol: float, p: int = 1, s: int | None = None,
           zeta: int = 8, seed: int = 0, sketch: str = "sparse_sign", S_U=None, S_V=None,
           trunc_tol: float = 1e-12, recover: str = "stored", sigma=None,
-          keep: bool = False) -> Result:
+          keep: bool = False, orth: str = "euclidean") -> Result:
     """Solve ``A X + X B = C1 C2^T`` with s-PKSM; returns low-rank ``X ~ X1 X2^T``.
+
+    ``orth = 'sketched'`` orthogonalises the truncated bases with the sketched inner product
+    (see ``Space.step_sketched``); the projected problem and everything after it are
+    unchanged.
 
     ``sigma`` (optional, length ``n1``) adds ``diag(sigma)`` to ``A``.  ``S_U``/``S_V``
     override the embeddings (e.g. the identity for the ``S = I`` special case).
@@ -212,8 +276,10 @@ def spksm(A, B, C1, C2, *, k: int, maxit: int, tol: float, p: int = 1, s: int | 
         return BT @ X
 
     keep_all = recover == "stored" or keep
-    U = Space(op_u, S_U, k, r, maxit, keep_all)
-    V = Space(op_v, S_V, k, r, maxit, keep_all)
+    if orth not in ("euclidean", "sketched"):
+        raise ValueError(orth)
+    U = Space(op_u, S_U, k, r, maxit, keep_all, orth=orth)
+    V = Space(op_v, S_V, k, r, maxit, keep_all, orth=orth)
     U.init(C1)
     V.init(C2)
     F11 = U.beta @ V.beta.T
