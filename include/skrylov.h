@@ -52,6 +52,8 @@ enum { SKR_FP64 = 0, SKR_MIXED = 1 };           /* bulk precision               
 enum { SKR_SKETCH_SPARSE_SIGN = 0,             /* subspace embedding (Algorithm 1)     */
        SKR_SKETCH_NONE = 2 };                   /* no embedding: Algorithm 2 (t-PKSM)   */
 enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
+enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in Algorithm 1  */
+       SKR_ORTH_SKETCHED = 1 };                 /* in the sketched inner product (app. A)    */
 
 /*
  * Solver parameters (Algorithm 1's inputs plus this library's choices).
@@ -80,6 +82,16 @@ enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
  *             skr_result_kernel_stats
  *   trunc_tol relative Frobenius cutoff of the low-rank factorisation of the projected
  *             solution Y (0 keeps everything)
+ *   orth      SKR_ORTH_EUCLIDEAN: the truncated block Gram-Schmidt and the QR of the new
+ *             block use the Euclidean inner product (Algorithm 1).  SKR_ORTH_SKETCHED: both
+ *             use <x, y>_S = (S x)^T (S y) instead (the alternative appendix A names):
+ *             S U_1 has orthonormal columns (ell = R factor of S C), h_{i,d} =
+ *             (S U_i)^T (S U~) in block modified Gram-Schmidt over the window, R from a
+ *             Cholesky QR twice of the sketched remainder, U_{d+1} = (U~ - sum_i U_i h_{i,d})
+ *             R^{-1}; S U_{d+1} comes from the sketch-space QR.  The sketched Galerkin
+ *             solution does not depend on the basis of the truncated space, so the factors
+ *             agree with SKR_ORTH_EUCLIDEAN up to rounding.  Needs the sparse sign sketch and
+ *             r <= 4, k <= 3 (SKR_ENOTSUP otherwise).
  */
 typedef struct {
   int32_t k;
@@ -94,10 +106,11 @@ typedef struct {
   int32_t recover;
   int32_t profile;
   double trunc_tol;
+  int32_t orth;
 } skr_params;
 
 /* Fill *p with defaults: k=2, maxit=200, p=20, zeta=8, s=0, tol=1e-6, seed=0,
- * SKR_FP64, sparse sign, stored basis, trunc_tol=1e-12.  Returns SKR_OK. */
+ * SKR_FP64, sparse sign, stored basis, trunc_tol=1e-12, Euclidean orthogonalisation.  Returns SKR_OK. */
 SKR_API int skr_params_default(skr_params* p);
 
 /*

@@ -29,7 +29,7 @@ def _shifted(A, sigma):
 
 def spksm_lyapunov(A, C, *, k: int, maxit: int, tol: float, p: int = 1, s: int | None = None, zeta: int = 8,
                    seed: int = 0, sketch: str = "sparse_sign", S=None, trunc_tol: float = 1e-12,
-                   recover: str = "stored", sigma=None, keep: bool = False):
+                   recover: str = "stored", sigma=None, keep: bool = False, orth: str = "euclidean"):
     """s-PKSM for ``(A + diag(sigma)) X + X (A + diag(sigma))^T = C C^T``."""
     As = _shifted(A, sigma)
     C = np.asarray(C, dtype=np.float64)
@@ -39,7 +39,7 @@ def spksm_lyapunov(A, C, *, k: int, maxit: int, tol: float, p: int = 1, s: int |
     if S is None:
         S = _sketch.make(sketch, n, s, zeta, _sketch.space_seeds(seed)[0])
     return spksm(As, As.T, C, C, k=k, maxit=maxit, tol=tol, p=p, s=s, S_U=S, S_V=S, trunc_tol=trunc_tol,
-                 recover=recover, keep=keep)
+                 recover=recover, keep=keep, orth=orth)
 
 
 def tpksm_lyapunov(A, C, *, k: int, maxit: int, tol: float, p: int = 1, trunc_tol: float = 1e-12,

@@ -12,6 +12,7 @@ SKR_EINVAL, SKR_EHIP, SKR_ENOMEM, SKR_ENOTSUP, SKR_EPROJ = -1, -2, -3, -4, -5
 SKR_FP64, SKR_MIXED = 0, 1
 SKR_SKETCH_SPARSE_SIGN, SKR_SKETCH_NONE = 0, 2
 SKR_RECOVER_STORED, SKR_RECOVER_TWO_PASS = 0, 1
+SKR_ORTH_EUCLIDEAN, SKR_ORTH_SKETCHED = 0, 1
 
 STATUS_NAMES = {SKR_OK: "converged", SKR_NOT_CONVERGED: "maxit", SKR_BREAKDOWN: "breakdown"}
 
@@ -30,6 +31,7 @@ class Params(ctypes.Structure):
         ("recover", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("trunc_tol", ctypes.c_double),
+        ("orth", ctypes.c_int32),
     ]
 
 

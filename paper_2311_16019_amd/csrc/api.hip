@@ -187,6 +187,7 @@ int skr_params_default(skr_params* p) {
   p->sketch = SKR_SKETCH_SPARSE_SIGN;
   p->recover = SKR_RECOVER_STORED;
   p->trunc_tol = 1e-12;
+  p->orth = SKR_ORTH_EUCLIDEAN;
   return SKR_OK;
 }
 

@@ -11,6 +11,10 @@
 // (one host synchronisation to read rho).  Finally the low-rank factors of Y and the
 // recovery X1 = U_d T_U^{-1} Y1, X2 = V_d T_V^{-1} Y2 from the stored basis or by
 // regenerating the basis from the stored Hessenberg blocks (two-pass).
+//
+// With the sketched inner product (params.orth) the step is SpMM, sketch of U~, the
+// sketch-space Gram-Schmidt and QR, one update pass over n rows, then the whitening; the
+// sketch of U_{d+1} is a by-product of the sketch-space QR.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -19,6 +23,7 @@
 #include "blockstep.hpp"
 #include "dense.hpp"
 #include "solver.hpp"
+#include "sorth.hpp"
 #include "whiten.hpp"
 
 namespace skr {
@@ -174,6 +179,8 @@ struct Space {
   DBuf<double> Pall, Gall, Xall, cgs;  // two-pass step: pending factors, Gram blocks, state
   DBuf<int> broken;
   DBuf<uint16_t> tab;
+  DBuf<double> skt, sring;  // sketched orthogonalisation: S U~ and the ring of S U_j
+  int nring = 0;
   // sketch of block j: two buffers by parity, so that the sketch of block j + 1 can be
   // written while block j's whitening still reads its own
   double* wbuf(int j) const { return (j & 1) ? w2.p : w.p; }
@@ -206,6 +213,10 @@ class Solver {
     SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN || p.sketch == SKR_SKETCH_NONE,
                 "sketch must be SKR_SKETCH_SPARSE_SIGN or SKR_SKETCH_NONE");
     sketched_ = p.sketch == SKR_SKETCH_SPARSE_SIGN;
+    SKR_REQUIRE(p.orth == SKR_ORTH_EUCLIDEAN || p.orth == SKR_ORTH_SKETCHED,
+                "orth must be SKR_ORTH_EUCLIDEAN or SKR_ORTH_SKETCHED");
+    sorth_ = p.orth == SKR_ORTH_SKETCHED;
+    SKR_REQUIRE(!sorth_ || sketched_, "the sketched inner product needs the sparse sign embedding");
     SKR_REQUIRE(p.recover == SKR_RECOVER_STORED || p.recover == SKR_RECOVER_TWO_PASS, "invalid recovery mode");
     SKR_REQUIRE(p.tol >= 0.0 && p.trunc_tol >= 0.0, "tolerances must be nonnegative");
     s_ = sketched_ ? p.s : 0;
@@ -221,6 +232,8 @@ class Solver {
     }
     ld_ = (p.maxit + 1) * r;
     fast_ = cgs_supported(r, p.k);
+    if (sorth_ && !fast_)
+      throw Error(SKR_ENOTSUP, "the sketched-inner-product block step needs r <= 4 and k <= 3");
     if (lyap_ && !fast_) throw Error(SKR_ENOTSUP, "the Lyapunov solve needs the two-pass block step (r <= 4, k <= 3)");
     if (lyap_ && p.recover != SKR_RECOVER_STORED)
       throw Error(SKR_ENOTSUP, "the Lyapunov solve needs stored-basis recovery");
@@ -332,7 +345,7 @@ class Solver {
     res->X1.alloc((size_t)sp_[0].n * ell);
     res->X2.alloc((size_t)sv.n * ell);
     if (p_.recover == SKR_RECOVER_STORED) {
-      if (fast_) {  // U_j = U'_j P_j: X = sum_j U'_j (P_j W[j])
+      if (fast_ && !sorth_) {  // U_j = U'_j P_j: X = sum_j U'_j (P_j W[j])
         const int g = std::max(1, std::min(4096, ceil_div((int64_t)dfinal * ell, 256)));
         hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sp_[0].Pall.p, W1.p, m);
         hipLaunchKernelGGL(apply_pending_kernel, dim3(g), dim3(256), 0, st_, r_, dfinal, ell, sv.Pall.p, W2.p, m);
@@ -393,6 +406,11 @@ class Solver {
     s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
     s.ell.alloc((size_t)r_ * r_);
     if (sketched_) s.tab.alloc((size_t)s.n * p_.zeta);
+    if (sorth_) {
+      s.nring = p_.k + 1;
+      s.skt.alloc((size_t)s_ * r_);
+      s.sring.alloc((size_t)s.nring * s_ * r_);
+    }
     s.H.zero(st_);
     s.Tm.zero(st_);
     s.small.zero(st_);
@@ -437,7 +455,7 @@ class Solver {
     CgsPass<T> a{};
     a.A = s.A;
     a.X = d >= 1 ? s.slot(d) : nullptr;
-    a.Pd = d >= 1 ? s.Pall.p + (size_t)d * r_ * r_ : nullptr;
+    a.Pd = (d >= 1 && !sorth_) ? s.Pall.p + (size_t)d * r_ * r_ : nullptr;
     a.Y = s.work.p;
     a.Unew = s.slot(d + 1);
     for (int i = 0; i < nw; ++i) a.W[i] = s.slot(i0 + i);
@@ -480,6 +498,10 @@ class Solver {
   }
 
   void init(const double* C1, const double* C2) {
+    if (sorth_) {
+      init_sorth(C1, C2);
+      return;
+    }
     if (fast_) {
       init_two_pass(C1, C2);
       init_sketch();
@@ -501,6 +523,52 @@ class Solver {
     init_sketch();
   }
 
+  // Sketched inner product: U_1 = C ell^{-1} with ell the R factor of S C, so that S U_1
+  // has orthonormal columns; S U_1 is taken from the QR of S C.
+  void init_sorth(const double* C1, const double* C2) {
+    CgsPass<T> a[2];
+    const double* Cs[2] = {C1, C2};
+    for (int q = 0; q < 2; ++q) {
+      a[q] = cgs_args(sp_[q], 0, 0, 1);
+      a[q].src = Cs[q];
+    }
+    launch_cgs_spmm<T>(r_, a[0], a[1], st_);  // U~ = C in the basis precision
+    build_tables();
+    sketch_work(st_);
+    launch_sorth(r_, (int)s_, 0, 1, 0, sorth_args(sp_[0], sp_[0].ell.p, r_, 1),
+                 sorth_args(sp_[1], sp_[1].ell.p, r_, 1), lyap_ ? 1 : 2, st_);
+    launch_cgs_pass2<T>(r_, 0, a[0], a[1], st_);  // U_1 = U~ ell^{-1}
+    whiten(0, 0, st_);
+    rhs_block();
+  }
+
+  SorthSpace sorth_args(Space<T>& s, double* H, int ldh, int j) {
+    return SorthSpace{s.skt.p, s.sring.p, s.nring, s.wbuf(j), s.cgs.p + cgs_coef_offset(), H, ldh, s.broken.p};
+  }
+
+  // w = S U~ for the block in the work buffer (both spaces)
+  void sketch_work(hipStream_t st) {
+    SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk};
+    SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk};
+    launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, nullptr, nullptr, lds_limit_, st);
+  }
+
+  void build_tables() {
+    const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
+    for (int i = 0; i < 2; ++i)
+      if (sp_[i].n > 0)  // the Lyapunov solve's empty placeholder space has no table
+        launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
+  }
+
+  // F11 = (T_U ell_U)(T_V ell_V)^T, the first block of the projected right-hand side
+  void rhs_block() {
+    F11_.alloc((size_t)r_ * r_);
+    hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p,
+                       second().Tm.p, ld_, second().ell.p, F11_.p);
+    check_launch("rhs_block");
+    rhs_block_host_.assign((size_t)r_ * r_, 0.0);
+  }
+
   // Sketch tables, S U_1, the first whitening step and F11 = beta_1 beta_2^T.
   void init_sketch() {
     if (!sketched_) {  // t-PKSM: T = I, so M = H and beta = ell
@@ -508,24 +576,13 @@ class Solver {
         hipLaunchKernelGGL(unit_diag_kernel, dim3(ceil_div(ld_, 256)), dim3(256), 0, st_, ld_, sp_[i].Tm.p, ld_);
         check_launch("unit_diag");
       }
-      F11_.alloc((size_t)r_ * r_);
-      hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p,
-                         second().Tm.p, ld_, second().ell.p, F11_.p);
-      check_launch("rhs_block");
-      rhs_block_host_.assign((size_t)r_ * r_, 0.0);
+      rhs_block();
       return;
     }
-    const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
-    for (int i = 0; i < 2; ++i)
-      if (sp_[i].n > 0)  // the Lyapunov solve's empty placeholder space has no table
-        launch_build_sketch_table(sp_[i].tab.p, sp_[i].n, p_.zeta, (int)(s_ / p_.zeta), seeds[i], st_);
+    build_tables();
     sketch(1, st_);
     whiten(0, 0, st_);
-    F11_.alloc((size_t)r_ * r_);
-    hipLaunchKernelGGL(rhs_block_kernel, dim3(1), dim3(256), 0, st_, r_, sp_[0].Tm.p, ld_, sp_[0].ell.p,
-                       second().Tm.p, ld_, second().ell.p, F11_.p);
-    check_launch("rhs_block");
-    rhs_block_host_.assign((size_t)r_ * r_, 0.0);
+    rhs_block();
   }
 
   // The second space of the equation: the V space, or the U space again for Lyapunov.
@@ -583,10 +640,44 @@ class Solver {
     after_step(d);
   }
 
+  // Sketched-inner-product block step: U~ = Op U_d and its sketch, the sketch-space
+  // Gram-Schmidt and QR (one workgroup per space), then U_{d+1} in one pass over n rows.
+  void block_step_sorth(int d) {
+    const int i0 = std::max(1, d - p_.k + 1), nw = d - i0 + 1;
+    CgsPass<T> a[2];
+    for (int q = 0; q < 2; ++q) a[q] = cgs_args(sp_[q], d, nw, i0);
+    prof_.begin(KF_SPMM);
+    launch_cgs_spmm<T>(r_, a[0], a[1], st_);
+    prof_.end();
+    prof_.begin(KF_SKETCH);
+    sketch_work(st_);
+    prof_.end();
+    // the sketch-space step writes the whitening input wbuf(d + 1), which the whitening of
+    // step d - 2 read
+    SKR_HIP(hipStreamWaitEvent(st_, ev_whiten_[(d + 1) & 1], 0));
+    prof_.begin(KF_REDUCE);
+    launch_sorth(r_, (int)s_, nw, i0, d, sorth_args(sp_[0], sp_[0].H.p, ld_, d + 1),
+                 sorth_args(sp_[1], sp_[1].H.p, ld_, d + 1), lyap_ ? 1 : 2, st_);
+    prof_.end();
+    prof_.begin(KF_UPDATE);
+    launch_cgs_pass2<T>(r_, nw, a[0], a[1], st_);
+    prof_.end();
+    after_step(d);
+  }
+
   // U_{d+1} is final: sketch it (stream aux_) and update Q, T (stream aux2_) concurrently
   // with the next block step; the sketch of block d + 2 overlaps this whitening.
   void after_step(int d) {
     if (!sketched_) return;  // t-PKSM: no embedding
+    if (sorth_) {  // S U_{d+1} is already in wbuf(d + 1)
+      SKR_HIP(hipEventRecord(ev_block_, st_));
+      SKR_HIP(hipStreamWaitEvent(aux2_, ev_block_, 0));
+      prof_.begin(KF_WHITEN, aux2_);
+      whiten(d, d, aux2_);
+      prof_.end();
+      SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 1], aux2_));
+      return;
+    }
     SKR_HIP(hipEventRecord(ev_block_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
     // the whitening of block d - 1 read the buffer that the sketch of block d + 1 writes
@@ -603,6 +694,10 @@ class Solver {
   }
 
   void block_step(int d) {
+    if (sorth_) {
+      block_step_sorth(d);
+      return;
+    }
     if (fast_) {
       block_step_two_pass(d);
       return;
@@ -739,6 +834,7 @@ class Solver {
   bool fast_ = false;      // two-pass block step (r <= 4, k <= 3)
   bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
   bool lyap_ = false;      // A X + X A^T = C1 C1^T on one Krylov space
+  bool sorth_ = false;     // truncated orthogonalisation in the sketched inner product
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;

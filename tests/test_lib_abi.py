@@ -38,9 +38,10 @@ def test_params_default_and_layout():
     lib = _lib.load()
     p = _lib.Params()
     assert lib.skr_params_default(ctypes.byref(p)) == 0
-    assert ctypes.sizeof(p) == 64
+    assert ctypes.sizeof(p) == 72
     assert (p.k, p.maxit, p.p, p.zeta, p.s) == (2, 200, 20, 8, 0)
     assert p.tol == 1e-6 and p.trunc_tol == 1e-12 and p.precision == _lib.SKR_FP64
+    assert p.orth == _lib.SKR_ORTH_EUCLIDEAN
     assert lib.skr_params_default(None) == _lib.SKR_EINVAL
     assert lib.skr_version().decode().startswith("skrylov")
 
