@@ -8,7 +8,7 @@
 namespace skr {
 namespace {
 
-constexpr int ST = 512;  // threads of the workgroup
+constexpr int ST = 1024;  // threads of the workgroup
 constexpr int SKW = 3;   // window blocks
 // Breakdown thresholds (not discussed in the paper; the same values as the FP64 oracle):
 // the orthogonalised sketch is negligible against S U~, or its R factor is numerically
@@ -16,25 +16,11 @@ constexpr int SKW = 3;   // window blocks
 constexpr double BREAK_NORM = 1e-12;
 constexpr double BREAK_DIAG = 1e-14;
 
-// out (r x r row-major, LDS) = X^T Y for s x R row-major X, Y.  Thread t owns rows
-// t, t + ST, ..; the order of the sums is fixed.
+// Workgroup sum of per-thread r x r partials into out (LDS); fixed order throughout.
 template <int R>
-__device__ void wg_cross(const double* X, const double* Y, int s, double* out, double* red) {
+__device__ void wg_reduce(const double (&acc)[R * R], double* out, double* red) {
   constexpr int RR = R * R;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  double acc[RR];
-#pragma unroll
-  for (int p = 0; p < RR; ++p) acc[p] = 0.0;
-#pragma unroll 4
-  for (int i = tid; i < s; i += ST) {
-    double x[R], y[R];
-    load_row<double, R>(X, i, x);
-    load_row<double, R>(Y, i, y);
-#pragma unroll
-    for (int a = 0; a < R; ++a)
-#pragma unroll
-      for (int b = 0; b < R; ++b) acc[a * R + b] += x[a] * y[b];
-  }
 #pragma unroll
   for (int p = 0; p < RR; ++p) {
     const double v = wave_sum(acc[p]);
@@ -49,71 +35,106 @@ __device__ void wg_cross(const double* X, const double* Y, int s, double* out, d
   __syncthreads();
 }
 
-// rows of w <- w M for an upper triangular M (row-major)
 template <int R>
-__device__ void right_upper(double* w, int s, const double* M) {
-#pragma unroll 4
-  for (int i = threadIdx.x; i < s; i += ST) {
-    double x[R], y[R];
-    load_row<double, R>(w, i, x);
+__device__ inline void cross_add(double (&acc)[R * R], const double (&x)[R], const double (&y)[R]) {
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      double t = 0.0;
+  for (int a = 0; a < R; ++a)
 #pragma unroll
-      for (int k = 0; k <= c; ++k) t += x[k] * M[k * R + c];
-      y[c] = t;
-    }
-    store_row<double, R>(w, i, y);
+    for (int b = 0; b < R; ++b) acc[a * R + b] += x[a] * y[b];
+}
+
+// y = x M for an upper triangular M (row-major)
+template <int R>
+__device__ inline void times_upper(const double (&x)[R], const double* M, double (&y)[R]) {
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k <= c; ++k) t += x[k] * M[k * R + c];
+    y[c] = t;
   }
 }
 
+// Thread t owns the rows t, t + ST, .. of every s x r array throughout, so an update and
+// the products that follow it need no barrier between them.  The passes over the s rows:
+//   0       ||w||_F^2 and h_1 = W_1^T w
+//   1 .. nw w -= W_i h_i (stored), then h_{i+1} = W_{i+1}^T w, or G = w^T w after the last
+//   nw + 1  G' = (w R1^{-1})^T (w R1^{-1})  (Cholesky QR, second pass; nothing stored)
+//   nw + 2  S U_{d+1} = w R1^{-1} R2^{-1} into the ring slot and the whitening input
 template <int R>
 __global__ void __launch_bounds__(ST) sorth_kernel(SorthSpace a0, SorthSpace a1, int s, int nw, int i0, int d) {
   constexpr int RR = R * R;
   const SorthSpace& a = blockIdx.x ? a1 : a0;
   __shared__ double red[(ST / 64) * RR];
-  __shared__ double h[SKW][RR], G[RR], R1[RR], R1i[RR], R2[RR], R2i[RR], RF[RR], RFi[RR];
-  __shared__ double nrm0;
+  __shared__ double h[SKW][RR], G[RR], N0[RR], R1[RR], R1i[RR], R2[RR], R2i[RR], RF[RR], RFi[RR];
   __shared__ int ok_sh;
   const int tid = threadIdx.x;
   double* w = a.w;
-  wg_cross<R>(w, w, s, G, red);
-  if (tid == 0) {
-    double t = 0.0;
-    for (int c = 0; c < R; ++c) t += G[c * R + c];
-    nrm0 = t;  // ||S U~||_F^2
-  }
-  // block Gram-Schmidt in the sketched inner product; a thread updates only the rows whose
-  // sums it owns, so no barrier is needed between a product and its update
-  for (int i = 0; i < nw; ++i) {
-    const double* Wi = a.ring + (size_t)((i0 + i) % a.nring) * s * R;
-    wg_cross<R>(Wi, w, s, h[i], red);
-#pragma unroll 4
-    for (int row = tid; row < s; row += ST) {
+  auto ring = [&](int j) -> double* { return a.ring + (size_t)(j % a.nring) * s * R; };
+  {
+    double acc[RR], nacc[RR];
+#pragma unroll
+    for (int p = 0; p < RR; ++p) acc[p] = nacc[p] = 0.0;
+    const double* W1 = nw > 0 ? ring(i0) : w;
+#pragma unroll 2
+    for (int i = tid; i < s; i += ST) {
       double x[R], y[R];
-      load_row<double, R>(Wi, row, x);
-      load_row<double, R>(w, row, y);
+      load_row<double, R>(w, i, y);
+      load_row<double, R>(W1, i, x);
+      cross_add<R>(acc, x, y);
+      cross_add<R>(nacc, y, y);
+    }
+    wg_reduce<R>(nacc, N0, red);
+    wg_reduce<R>(acc, nw > 0 ? h[0] : G, red);
+  }
+  for (int j = 0; j < nw; ++j) {
+    const double* Wj = ring(i0 + j);
+    const double* Wn = j + 1 < nw ? ring(i0 + j + 1) : w;
+    double acc[RR];
+#pragma unroll
+    for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+#pragma unroll 2
+    for (int i = tid; i < s; i += ST) {
+      double x[R], y[R], z[R];
+      load_row<double, R>(Wj, i, x);
+      load_row<double, R>(w, i, y);
 #pragma unroll
       for (int b = 0; b < R; ++b)
 #pragma unroll
-        for (int c = 0; c < R; ++c) y[b] -= x[c] * h[i][c * R + b];
-      store_row<double, R>(w, row, y);
+        for (int c = 0; c < R; ++c) y[b] -= x[c] * h[j][c * R + b];
+      store_row<double, R>(w, i, y);
+      if (j + 1 < nw) {
+        load_row<double, R>(Wn, i, z);
+      } else {
+#pragma unroll
+        for (int c = 0; c < R; ++c) z[c] = y[c];
+      }
+      cross_add<R>(acc, z, y);
     }
+    wg_reduce<R>(acc, j + 1 < nw ? h[j + 1] : G, red);
   }
   // Cholesky QR twice of the remainder: w = q R2 R1
-  wg_cross<R>(w, w, s, G, red);
   if (tid == 0) {
-    double t = 0.0;
-    for (int c = 0; c < R; ++c) t += G[c * R + c];
-    bool ok = t >= BREAK_NORM * BREAK_NORM * nrm0 && chol_upper(G, R1, R);
+    double t0 = 0.0, t = 0.0;
+    for (int c = 0; c < R; ++c) { t0 += N0[c * R + c]; t += G[c * R + c]; }
+    bool ok = t >= BREAK_NORM * BREAK_NORM * t0 && chol_upper(G, R1, R);
     if (ok) inv_upper(R1, R1i, R);
     ok_sh = ok ? 1 : 0;
   }
   __syncthreads();
   bool ok = ok_sh != 0;  // uniform over the workgroup
   if (ok) {
-    right_upper<R>(w, s, R1i);
-    wg_cross<R>(w, w, s, G, red);
+    double acc[RR];
+#pragma unroll
+    for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+#pragma unroll 2
+    for (int i = tid; i < s; i += ST) {
+      double x[R], y[R];
+      load_row<double, R>(w, i, x);
+      times_upper<R>(x, R1i, y);
+      cross_add<R>(acc, y, y);
+    }
+    wg_reduce<R>(acc, G, red);
   }
   if (tid == 0) {
     if (ok) ok = chol_upper(G, R2, R);
@@ -128,25 +149,18 @@ __global__ void __launch_bounds__(ST) sorth_kernel(SorthSpace a0, SorthSpace a1,
     }
     if (!ok) {
       atomicMin(a.broken, d);
-      for (int p = 0; p < RR; ++p) { RF[p] = 0.0; RFi[p] = 0.0; R2i[p] = 0.0; }
+      for (int p = 0; p < RR; ++p) { RF[p] = 0.0; RFi[p] = 0.0; }
     }
     ok_sh = ok ? 1 : 0;
   }
   __syncthreads();
-  ok = ok_sh != 0;
-  // S U_{d+1} = w R2^{-1} (zero after a breakdown)
-  double* out = a.ring + (size_t)((d + 1) % a.nring) * s * R;
-#pragma unroll 4
+  // S U_{d+1} = w R^{-1} (zero after a breakdown)
+  double* out = ring(d + 1);
+#pragma unroll 2
   for (int i = tid; i < s; i += ST) {
     double x[R], y[R];
     load_row<double, R>(w, i, x);
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k <= c; ++k) t += x[k] * R2i[k * R + c];
-      y[c] = ok ? t : 0.0;
-    }
+    times_upper<R>(x, RFi, y);
     store_row<double, R>(out, i, y);
     store_row<double, R>(a.wout, i, y);
   }
