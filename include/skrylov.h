@@ -50,6 +50,7 @@ enum {
 
 enum { SKR_FP64 = 0, SKR_MIXED = 1 };           /* bulk precision                       */
 enum { SKR_SKETCH_SPARSE_SIGN = 0,             /* subspace embedding (Algorithm 1)     */
+       SKR_SKETCH_SRHT = 1,                     /* subsampled randomized DCT (Sec. 6)   */
        SKR_SKETCH_NONE = 2 };                   /* no embedding: Algorithm 2 (t-PKSM)   */
 enum { SKR_RECOVER_STORED = 0, SKR_RECOVER_TWO_PASS = 1 };
 enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in Algorithm 1  */
@@ -68,7 +69,14 @@ enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in 
  *   zeta      nonzeros per column of the sparse sign embedding (default 8)
  *   precision SKR_FP64, or SKR_MIXED (FP32 sparse products, orthogonalisation and sketch
  *             input; FP64 sketched quantities, projected solve and residual estimate)
- *   sketch    SKR_SKETCH_SPARSE_SIGN: s-PKSM (Algorithm 1).  SKR_SKETCH_NONE: the truncated
+ *   sketch    SKR_SKETCH_SPARSE_SIGN: s-PKSM (Algorithm 1) with the sparse sign embedding
+ *             (zeta nonzeros per column).  SKR_SKETCH_SRHT: s-PKSM with the subsampled
+ *             randomized DCT of the paper's experiments, S x = sqrt(n/s) DCT2(E x)[rows]
+ *             (orthonormal DCT-II; E_j = -1 when the low bit of SplitMix64 output j+1 from
+ *             the space's seed is set; rows = the s indices i with the smallest output i+1
+ *             of the generator started at mix64(seed), ascending); needs s <= n and
+ *             n = N1 N2 with N1 = P Q, P, Q <= 64, N1 <= 3072, N2 <= 4096 (SKR_ENOTSUP
+ *             otherwise); zeta is ignored.  SKR_SKETCH_NONE: the truncated
  *             Arnoldi method t-PKSM (Algorithm 2, appendix A): the same block steps without
  *             an embedding, the projected equation H_d Y + Y G_d^T = E_1 beta_1 beta_2^T E_1^T
  *             on the truncated block Hessenberg matrices (beta = R factors of C1, C2), the

@@ -135,7 +135,8 @@ def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64
     prm.seed, prm.zeta, prm.trunc_tol = int(seed) & (2**64 - 1), int(zeta), float(trunc_tol)
     prm.precision = {"fp64": _lib.SKR_FP64, "mixed": _lib.SKR_MIXED}[precision]
     prm.recover = {"stored": _lib.SKR_RECOVER_STORED, "two_pass": _lib.SKR_RECOVER_TWO_PASS}[recover]
-    prm.sketch = {"sparse_sign": _lib.SKR_SKETCH_SPARSE_SIGN, "none": _lib.SKR_SKETCH_NONE}[sketch]
+    prm.sketch = {"sparse_sign": _lib.SKR_SKETCH_SPARSE_SIGN, "srht": _lib.SKR_SKETCH_SRHT,
+                  "none": _lib.SKR_SKETCH_NONE}[sketch]
     prm.orth = {"euclidean": _lib.SKR_ORTH_EUCLIDEAN, "sketched": _lib.SKR_ORTH_SKETCHED}[orth]
     prm.profile = 1 if profile else 0
     return prm
@@ -194,7 +195,8 @@ def solve(A: Operator, B: Operator, C1, C2, stream=None, **params) -> Result:
 
     ``params``: k, maxit, p, s, tol, seed, zeta, precision ('fp64' | 'mixed'),
     recover ('stored' | 'two_pass'), trunc_tol, sketch ('sparse_sign': s-PKSM, Algorithm 1;
-    'none': t-PKSM, Algorithm 2, no embedding), orth ('euclidean' | 'sketched': truncated
+    'srht': s-PKSM with the subsampled randomized DCT of Sec. 6; 'none': t-PKSM, Algorithm 2,
+    no embedding), orth ('euclidean' | 'sketched': truncated
     Gram-Schmidt and QR in the sketched inner product, appendix A).
     """
     return _run("skr_solve", A, B, C1, C2, stream, **params)

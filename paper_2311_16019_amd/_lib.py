@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libskrylov.so")
 SKR_OK, SKR_NOT_CONVERGED, SKR_BREAKDOWN = 0, 1, 2
 SKR_EINVAL, SKR_EHIP, SKR_ENOMEM, SKR_ENOTSUP, SKR_EPROJ = -1, -2, -3, -4, -5
 SKR_FP64, SKR_MIXED = 0, 1
-SKR_SKETCH_SPARSE_SIGN, SKR_SKETCH_NONE = 0, 2
+SKR_SKETCH_SPARSE_SIGN, SKR_SKETCH_SRHT, SKR_SKETCH_NONE = 0, 1, 2
 SKR_RECOVER_STORED, SKR_RECOVER_TWO_PASS = 0, 1
 SKR_ORTH_EUCLIDEAN, SKR_ORTH_SKETCHED = 0, 1
 

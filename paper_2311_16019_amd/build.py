@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libskrylov.so")
 ARCH = "gfx950"
 
-SOURCES = ["runtime.hip", "op.hip", "blockstep.hip", "block_cgs.hip", "whiten.hip", "sorth.hip", "dense.hip", "gauss_jordan.hip", "proj.hip", "solver.hip", "api.hip"]
+SOURCES = ["runtime.hip", "op.hip", "blockstep.hip", "block_cgs.hip", "whiten.hip", "sorth.hip", "srht.hip", "dense.hip", "gauss_jordan.hip", "proj.hip", "solver.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

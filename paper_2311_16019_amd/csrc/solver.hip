@@ -24,6 +24,7 @@
 #include "dense.hpp"
 #include "solver.hpp"
 #include "sorth.hpp"
+#include "srht.hpp"
 #include "whiten.hpp"
 
 namespace skr {
@@ -181,6 +182,9 @@ struct Space {
   DBuf<uint16_t> tab;
   DBuf<double> skt, sring;  // sketched orthogonalisation: S U~ and the ring of S U_j
   int nring = 0;
+  SrhtPlan srht;                   // DCT embedding: factorisation and sampled rows
+  DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
+  DBuf<int> sroff, srsamp;
   // sketch of block j: two buffers by parity, so that the sketch of block j + 1 can be
   // written while block j's whitening still reads its own
   double* wbuf(int j) const { return (j & 1) ? w2.p : w.p; }
@@ -210,13 +214,14 @@ class Solver {
     SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
     SKR_REQUIRE(p.p >= 1, "p must be >= 1");
     SKR_REQUIRE(p.zeta >= 1 && p.zeta <= 64, "zeta must be in [1, 64]");
-    SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN || p.sketch == SKR_SKETCH_NONE,
-                "sketch must be SKR_SKETCH_SPARSE_SIGN or SKR_SKETCH_NONE");
-    sketched_ = p.sketch == SKR_SKETCH_SPARSE_SIGN;
+    SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN || p.sketch == SKR_SKETCH_SRHT || p.sketch == SKR_SKETCH_NONE,
+                "sketch must be SKR_SKETCH_SPARSE_SIGN, SKR_SKETCH_SRHT or SKR_SKETCH_NONE");
+    sketched_ = p.sketch != SKR_SKETCH_NONE;
+    srht_ = p.sketch == SKR_SKETCH_SRHT;
     SKR_REQUIRE(p.orth == SKR_ORTH_EUCLIDEAN || p.orth == SKR_ORTH_SKETCHED,
                 "orth must be SKR_ORTH_EUCLIDEAN or SKR_ORTH_SKETCHED");
     sorth_ = p.orth == SKR_ORTH_SKETCHED;
-    SKR_REQUIRE(!sorth_ || sketched_, "the sketched inner product needs the sparse sign embedding");
+    SKR_REQUIRE(!sorth_ || sketched_, "the sketched inner product needs an embedding");
     SKR_REQUIRE(p.recover == SKR_RECOVER_STORED || p.recover == SKR_RECOVER_TWO_PASS, "invalid recovery mode");
     SKR_REQUIRE(p.tol >= 0.0 && p.trunc_tol >= 0.0, "tolerances must be nonnegative");
     s_ = sketched_ ? p.s : 0;
@@ -225,9 +230,11 @@ class Solver {
         s_ = 2 * (int64_t)p.maxit * r;
         s_ = (s_ + p.zeta - 1) / p.zeta * p.zeta;
       }
-      SKR_REQUIRE(s_ % p.zeta == 0, "s must be a multiple of zeta");
+      if (!srht_) {
+        SKR_REQUIRE(s_ % p.zeta == 0, "s must be a multiple of zeta");
+        SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
+      }
       SKR_REQUIRE(s_ >= (int64_t)(p.maxit + 1) * r, "s must be at least (maxit+1) r");
-      SKR_REQUIRE(s_ / p.zeta <= 32768, "s / zeta must not exceed 32768");
       SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
     }
     ld_ = (p.maxit + 1) * r;
@@ -244,6 +251,7 @@ class Solver {
     lds_limit_ = std::max<size_t>(65536, prop.sharedMemPerBlock);
     setup(sp_[0], A, tu);
     setup(sp_[1], lyap_ ? nullptr : B, tv);
+    if (srht_) setup_srht();
   }
 
   ~Solver() {
@@ -398,14 +406,14 @@ class Solver {
     }
     s.broken.alloc(1);
     s.nchunk = sketch_chunks(s.n, lyap_ ? 1 : 2);
-    s.skpart.alloc((size_t)s.nchunk * s_ * r_);
+    if (!srht_) s.skpart.alloc((size_t)s.nchunk * s_ * r_);
     s.w.alloc((size_t)s_ * r_);
     s.w2.alloc((size_t)s_ * r_);
     s.c1.alloc((size_t)ld_ * r_);
     s.c2.alloc((size_t)ld_ * r_);
     s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
     s.ell.alloc((size_t)r_ * r_);
-    if (sketched_) s.tab.alloc((size_t)s.n * p_.zeta);
+    if (sketched_ && !srht_) s.tab.alloc((size_t)s.n * p_.zeta);
     if (sorth_) {
       s.nring = p_.k + 1;
       s.skt.alloc((size_t)s_ * r_);
@@ -542,18 +550,60 @@ class Solver {
     rhs_block();
   }
 
+  // DCT embedding of each space: plan (host, cached), stage-1 workspace, sampled rows
+  void setup_srht() {
+    const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
+    for (int q = 0; q < 2; ++q) {
+      Space<T>& s = sp_[q];
+      if (s.n == 0) continue;
+      s.srht = srht_plan(s.n, (int)s_, seeds[q]);
+      s.srz.alloc(srht_z_doubles(s.n, r_));
+      s.srraw.alloc((size_t)s_ * r_);
+      s.sroff.alloc(s.srht.soff.size());
+      s.srsamp.alloc(s.srht.samp.size());
+      SKR_HIP(hipMemcpyAsync(s.sroff.p, s.srht.soff.data(), sizeof(int) * s.srht.soff.size(), hipMemcpyHostToDevice,
+                             st_));
+      SKR_HIP(hipMemcpyAsync(s.srsamp.p, s.srht.samp.data(), sizeof(int) * s.srht.samp.size(),
+                             hipMemcpyHostToDevice, st_));
+    }
+  }
+
+  SrhtSpace<T> srht_args(Space<T>& s, const T* U, double* w, const double* pend) {
+    SrhtSpace<T> a{};
+    a.U = U;
+    a.Z = s.srz.p;
+    a.soff = s.sroff.p;
+    a.samp = s.srsamp.p;
+    a.wraw = pend ? s.srraw.p : w;
+    a.w = w;
+    a.Pend = pend;
+    a.n = s.n;
+    a.N1 = s.srht.N1;
+    a.N2 = s.srht.N2;
+    a.P = s.srht.P;
+    a.Q = s.srht.Q;
+    a.seed = s.srht.seed;
+    return a;
+  }
+
   SorthSpace sorth_args(Space<T>& s, double* H, int ldh, int j) {
     return SorthSpace{s.skt.p, s.sring.p, s.nring, s.wbuf(j), s.cgs.p + cgs_coef_offset(), H, ldh, s.broken.p};
   }
 
   // w = S U~ for the block in the work buffer (both spaces)
   void sketch_work(hipStream_t st) {
+    if (srht_) {
+      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].work.p, sp_[0].skt.p, nullptr),
+                     srht_args(sp_[1], sp_[1].work.p, sp_[1].skt.p, nullptr), lyap_ ? 1 : 2, lds_limit_, st);
+      return;
+    }
     SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk};
     SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk};
     launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, nullptr, nullptr, lds_limit_, st);
   }
 
   void build_tables() {
+    if (srht_) return;  // the DCT embedding draws its signs on the fly
     const uint64_t seeds[2] = {p_.seed, mix64_host(p_.seed + 1)};
     for (int i = 0; i < 2; ++i)
       if (sp_[i].n > 0)  // the Lyapunov solve's empty placeholder space has no table
@@ -595,6 +645,13 @@ class Solver {
   }
 
   void sketch(int j, hipStream_t s) {
+    if (srht_) {
+      const size_t off = (size_t)j * r_ * r_;
+      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].slot(j), sp_[0].wbuf(j), fast_ ? sp_[0].Pall.p + off : nullptr),
+                     srht_args(sp_[1], sp_[1].slot(j), sp_[1].wbuf(j), fast_ ? sp_[1].Pall.p + off : nullptr),
+                     lyap_ ? 1 : 2, lds_limit_, s);
+      return;
+    }
     SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].wbuf(j), sp_[0].n, sp_[0].nchunk};
     SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].wbuf(j), sp_[1].n, sp_[1].nchunk};
     const size_t off = (size_t)j * r_ * r_;
@@ -835,6 +892,7 @@ class Solver {
   bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
   bool lyap_ = false;      // A X + X A^T = C1 C1^T on one Krylov space
   bool sorth_ = false;     // truncated orthogonalisation in the sketched inner product
+  bool srht_ = false;      // subsampled randomized DCT embedding instead of the sparse sign one
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;

@@ -1,0 +1,113 @@
+"""GPU parity of s-PKSM with the subsampled randomized DCT embedding (sketch = 'srht', the
+embedding of the paper's experiments, Sec. 6) against the FP64 oracle, through the C ABI.
+
+The oracle applies the embedding with scipy's orthonormal DCT-II; the GPU takes it through a
+two-stage DFT of the reordered columns that forms only the sampled outputs.  Both draw the
+signs and the sampled rows from SplitMix64 by the same published definition.  Same protocol
+and bars as the sparse sign parity tests: fixed d on both sides, product distance <= 1e-6
+(FP64) / 1e-4 (mixed), residual estimates within 1e-6 / 1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_ops, gpu_solve, history_ratio, oracle_solve, product_distance, to_dev, torch_cuda
+from oracle.lowrank import rel_distance
+from oracle.lyapunov import spksm_lyapunov
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-6, 1e-6), "mixed": (1e-4, 1e-3)}
+
+# n = m^2 or m^3: 2025 = 45^2, 1369 = 37^2 (a prime square: N1 = 37, Q = 1), 1089 = 3^2 11^2,
+# 1331 = 11^3
+CASES = [
+    ("laplace2d_64", 45, 1, dict(k=2, maxit=40, p=10, s=336, seed=4001)),
+    ("convdiff2d_1000", 37, 4, dict(k=3, maxit=24, p=8, s=800, seed=4002)),
+    ("reaction2d_500", 33, 2, dict(k=2, maxit=30, p=10, s=496, seed=4004)),
+    ("aniso3d_100", 11, 3, dict(k=2, maxit=10, p=5, s=400, seed=4003)),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-m{c[1]}-r{c[2]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("orth", ["euclidean", "sketched"])
+def test_srht_fixed_d_parity(case, precision, orth):
+    name, m, r, prm = case
+    cfg = make_config(name, m=m, r=r)
+    print(f"srht case {name} m={m} r={r} {precision} {orth}", flush=True)
+    g, _ = gpu_solve(cfg, precision=precision, tol=0.0, sketch="srht", orth=orth, **prm)
+    o = oracle_solve(cfg, tol=0.0, sketch="srht", orth=orth, **prm)
+    assert g.iters == o.d == prm["maxit"]
+    tol_x, tol_h = TOL[precision]
+    dist, hr = product_distance(g, o), history_ratio(g, o)
+    assert dist <= tol_x, dist
+    assert hr <= tol_h, hr
+
+
+@pytest.mark.parametrize("recover", ["stored", "two_pass"])
+def test_srht_converged_run(recover):
+    cfg = make_config("convdiff2d_1000", m=40, r=2)
+    prm = dict(k=2, maxit=150, p=5, tol=1e-7, s=1200, seed=4010)
+    print(f"srht converged convdiff m=40 {recover}", flush=True)
+    g, _ = gpu_solve(cfg, recover=recover, sketch="srht", **prm)
+    o = oracle_solve(cfg, sketch="srht", **prm)
+    assert g.status == o.status == "converged"
+    assert g.iters == o.d
+    assert product_distance(g, o) <= 1e-6
+    assert history_ratio(g, o) <= 1e-6
+
+
+def test_srht_lyapunov():
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=37, r=4)
+    prm = dict(k=3, maxit=24, p=8, s=800, seed=4020, tol=0.0)
+    for precision in ("fp64", "mixed"):
+        print(f"srht Lyapunov convdiff m=37 {precision}", flush=True)
+        A, _ = gpu_ops(cfg)
+        g = skr.lyap_solve(A, to_dev(cfg["C1"]), precision=precision, sketch="srht", **prm)
+        torch_cuda().cuda.synchronize()
+        o = spksm_lyapunov(cfg["A"], cfg["C1"], sigma=cfg.get("sigma"), sketch="srht", **prm)
+        assert g.iters == o.d == prm["maxit"]
+        dist = rel_distance(g.X1.cpu().numpy(), g.X2.cpu().numpy(), o.X1, o.X2)
+        assert dist <= TOL[precision][0], (precision, dist)
+        assert history_ratio(g, o) <= TOL[precision][1]
+
+
+def test_srht_unsupported_sizes_are_rejected():
+    import paper_2311_16019_amd as skr
+    import scipy.sparse as sp
+    from workloads.stencil import CSR
+    n = 4099  # a prime above the longest second-stage sequence
+    rng = np.random.Generator(np.random.PCG64(7))
+    A = CSR.from_scipy(sp.diags(np.linspace(1, 2, n)).tocsr())
+    cfg = dict(A=A, B=A, sigma=None, C1=rng.standard_normal((n, 1)), C2=rng.standard_normal((n, 1)))
+    Ad, Bd = gpu_ops(cfg)
+    with pytest.raises(skr.SkrError) as ei:
+        skr.solve(Ad, Bd, to_dev(cfg["C1"]), to_dev(cfg["C2"]), maxit=5, p=5, s=48, sketch="srht")
+    assert ei.value.code == -4
+    cfg = make_config("convdiff2d_1000", m=10, r=2)
+    Ad, Bd = gpu_ops(cfg)
+    with pytest.raises(skr.SkrError) as ei:  # more sampled rows than n
+        skr.solve(Ad, Bd, to_dev(cfg["C1"]), to_dev(cfg["C2"]), maxit=60, p=5, s=160, sketch="srht")
+    assert ei.value.code == -1
+
+
+def test_srht_full_size_convdiff_fixed_d():
+    """The 1000 x 1000 convection-diffusion pair (n = 1e6, r = 4, k = 3, s = 8000) with the
+    DCT embedding, compared with the oracle at d = 20."""
+    cfg = make_config("convdiff2d_1000")
+    prm = dict(k=3, maxit=20, p=20, s=cfg["s"], tol=0.0, seed=cfg["sketch_seed"])
+    o = None
+    for precision in ("fp64", "mixed"):
+        print(f"srht full-size convdiff {precision}", flush=True)
+        g, _ = gpu_solve(cfg, precision=precision, sketch="srht", **prm)
+        if o is None:
+            o = oracle_solve(cfg, sketch="srht", **prm)
+        dist = product_distance(g, o)
+        assert dist <= TOL[precision][0], (precision, dist)
+        assert history_ratio(g, o) <= TOL[precision][1]
