@@ -67,6 +67,28 @@ def test_srht_full_sampling_is_orthogonal():
     assert np.allclose(S.T @ S, np.eye(n), atol=1e-13)
 
 
+@pytest.mark.parametrize("n,s", [(7, 3), (12, 5), (15, 15)])
+def test_srht_entries_match_the_dct_definition(n, s):
+    """Brute force from the definitions: entry (i, j) of S = sqrt(n/s) D N E is
+    sqrt(n/s) sqrt(2/n) c_k cos(pi k (2j+1) / (2n)) E_j with k = rows[i], c_0 = 1/sqrt(2),
+    c_k = 1 otherwise (the orthonormal DCT-II); E_j is -1 exactly when output j+1 of SplitMix64
+    from the seed is odd; rows are the s indices with the smallest outputs of the generator
+    started at mix64(seed), ascending (a transposed N, signs applied after the transform, a
+    wrong scale or a wrong draw all fail this)."""
+    seed = 12345
+    S = sketch.SRHT(n, s, seed).dense()
+    outs = sketch.splitmix64_stream(seed, n)
+    E = [-1.0 if z & 1 else 1.0 for z in outs]
+    keys = sketch.splitmix64_stream(sketch.mix64_int(seed), n)
+    rows = sorted(sorted(range(n), key=lambda i: (keys[i], i))[:s])
+    ref = np.zeros((s, n))
+    for i, k in enumerate(rows):
+        ck = 1.0 / np.sqrt(2.0) if k == 0 else 1.0
+        for j in range(n):
+            ref[i, j] = np.sqrt(n / s) * np.sqrt(2.0 / n) * ck * np.cos(np.pi * k * (2 * j + 1) / (2 * n)) * E[j]
+    assert np.abs(S - ref).max() < 1e-13
+
+
 def test_srht_norm_preserved_in_expectation():
     n, s = 256, 64
     x = np.random.Generator(np.random.PCG64(3)).standard_normal(n)
