@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-lyapunov", action="store_true", help="skip the Lyapunov comparison solve")
     ap.add_argument("--no-sorth", action="store_true",
                     help="skip the solve with the sketched-inner-product orthogonalisation")
+    ap.add_argument("--no-srht", action="store_true", help="skip the solve with the subsampled randomized DCT")
     ap.add_argument("--concurrent", action="store_true",
                     help="run the forward and the adjoint solve of a step concurrently (two host threads, "
                          "one stream each)")
@@ -324,6 +325,8 @@ def main():
         out["tpksm_forward"] = tpksm_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True))
     if not args.no_sorth:
         out["sketched_orth_forward"] = sorth_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True), f)
+    if not args.no_srht:
+        out["srht_forward"] = srht_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True), f)
     if not args.no_lyapunov:
         out["lyapunov_forward"] = lyapunov_leg(skr, torch, A, C1, params(args.precision, profile=True), f)
     if not args.no_cpu_baseline:
@@ -346,6 +349,25 @@ def sorth_leg(skr, torch, A, B, C1, C2, prm, f_euc):
                                    recovery=round(fs.ms_recover, 2)),
                 euclidean_forward_block_steps_ms=round(f_euc.ms_steps, 2),
                 kernel_families={k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in fs.kernels.items()},
+                rho_rel=fs.rho_rel, true_residual=skr.true_residual(A, B, fs.X1, fs.X2, C1, C2),
+                projected=fs.proj)
+
+
+def srht_leg(skr, torch, A, B, C1, C2, prm, f_sparse):
+    """The forward solve with the subsampled randomized DCT embedding of the paper's
+    experiments (Sec. 6) instead of the sparse sign one, same problem, s and window."""
+    prm["sketch"] = "srht"
+    skr.solve(A, B, C1, C2, **prm)  # warm-up (also builds the sampled-row plans)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fs = skr.solve(A, B, C1, C2, **prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    fam = {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in fs.kernels.items()}
+    return dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fs.iters / el, 1), iters=fs.iters,
+                time_split_ms=dict(block_steps=round(fs.ms_steps, 2), projected_solves=round(fs.ms_proj, 2),
+                                   recovery=round(fs.ms_recover, 2)),
+                sparse_sign_forward_block_steps_ms=round(f_sparse.ms_steps, 2), kernel_families=fam,
                 rho_rel=fs.rho_rel, true_residual=skr.true_residual(A, B, fs.X1, fs.X2, C1, C2),
                 projected=fs.proj)
 

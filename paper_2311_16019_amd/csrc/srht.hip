@@ -20,6 +20,7 @@ constexpr int PQMAX = 64;     // largest direct DFT length of stage 1
 constexpr int N1MAX = 3072;   // stage-1 sequence length (LDS: tables + one column)
 constexpr int N2MAX = 4096;   // stage-2 sequence length (LDS: twiddles + one column)
 constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
+constexpr int LD = 8;         // global loads in flight per thread in the staging loops
 
 __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -27,7 +28,7 @@ __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// exp(-2 pi i t / N) into (re, im)
+// exp(-2 pi i t / N) into (re, im), 0 <= t < N
 __device__ inline void twiddle(int64_t t, int64_t N, double& re, double& im) {
   double sn, cs;
   sincospi(2.0 * (double)t / (double)N, &sn, &cs);
@@ -46,22 +47,45 @@ __global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtS
   double* wN1 = sm;              // 2 N1
   double* wP = wN1 + 2 * N1;     // 2 P
   double* wQ = wP + 2 * P;       // 2 Q
-  double* Ts = wQ + 2 * Q;       // 2 cc N1
+  double* bP = wQ + 2 * Q;       // 2 P: w_n^{b k1a}
+  double* bQ = bP + 2 * P;       // 2 Q: w_n^{b P k1b}
+  double* Ts = bQ + 2 * Q;       // 2 cc N1
   double* xs = Ts + 2 * cc * N1; // cc N1
-  for (int j = tid; j < N1; j += S1T) twiddle(j, N1, wN1[2 * j], wN1[2 * j + 1]);
-  for (int j = tid; j < P; j += S1T) twiddle(j, P, wP[2 * j], wP[2 * j + 1]);
-  for (int j = tid; j < Q; j += S1T) twiddle(j, Q, wQ[2 * j], wQ[2 * j + 1]);
   const int64_t n = a.n, h = (n + 1) / 2;
+  for (int j = tid; j < N1; j += S1T) twiddle(j, N1, wN1[2 * j], wN1[2 * j + 1]);
+  for (int j = tid; j < P; j += S1T) {
+    twiddle(j, P, wP[2 * j], wP[2 * j + 1]);
+    twiddle(((int64_t)b * j) % n, n, bP[2 * j], bP[2 * j + 1]);
+  }
+  for (int j = tid; j < Q; j += S1T) {
+    twiddle(j, Q, wQ[2 * j], wQ[2 * j + 1]);
+    twiddle(((int64_t)b * P * j) % n, n, bQ[2 * j], bQ[2 * j + 1]);
+  }
   for (int c0 = 0; c0 < r; c0 += cc) {
     const int ncol = min(cc, r - c0);
     __syncthreads();  // tables written, previous chunk consumed
-    // v[N2 a + b] with v the even entries of y = E x followed by the odd ones reversed
-    for (int e = tid; e < N1 * ncol; e += S1T) {
-      const int aa = e / ncol, cl = e % ncol;
-      const int64_t m = (int64_t)N2 * aa + b;
-      const int64_t row = m < h ? 2 * m : 2 * (n - 1 - m) + 1;
-      const double sg = (splitmix_mix(a.seed + (uint64_t)(row + 1) * GOLDEN) & 1ull) ? -1.0 : 1.0;
-      xs[cl * N1 + aa] = sg * static_cast<double>(a.U[row * r + c0 + cl]);
+    // v[N2 a + b] with v the even entries of y = E x followed by the odd ones reversed;
+    // LD loads per thread are issued before any of them is used
+    for (int e0 = 0; e0 < N1 * ncol; e0 += LD * S1T) {
+      double val[LD];
+      int64_t rows[LD];
+#pragma unroll
+      for (int u = 0; u < LD; ++u) {
+        const int e = e0 + u * S1T + tid;
+        const int aa = e / ncol, cl = e % ncol;
+        const int64_t m = (int64_t)N2 * aa + b;
+        rows[u] = m < h ? 2 * m : 2 * (n - 1 - m) + 1;
+        val[u] = e < N1 * ncol ? static_cast<double>(a.U[rows[u] * r + c0 + cl]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < LD; ++u) {
+        const int e = e0 + u * S1T + tid;
+        if (e < N1 * ncol) {
+          const int aa = e / ncol, cl = e % ncol;
+          const double sg = (splitmix_mix(a.seed + (uint64_t)(rows[u] + 1) * GOLDEN) & 1ull) ? -1.0 : 1.0;
+          xs[cl * N1 + aa] = sg * val[u];
+        }
+      }
     }
     __syncthreads();
     // P-point DFTs over a1 (a = Q a1 + a2), times w_N1^{a2 k1a}
@@ -98,9 +122,10 @@ __global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtS
         if (idx >= Q) idx -= Q;
       }
       const int k1 = k1a + P * k1b;
-      double tr, ti;
-      twiddle(((int64_t)b * k1) % n, n, tr, ti);
-      double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N1 + k1) * N2 + b);
+      // w_n^{b k1} = w_n^{b k1a} w_n^{b P k1b}
+      const double ur = bP[2 * k1a], ui = bP[2 * k1a + 1], vr = bQ[2 * k1b], vi = bQ[2 * k1b + 1];
+      const double tr = ur * vr - ui * vi, ti = ur * vi + ui * vr;
+      double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N2 + b) * N1 + k1);  // [column][b][k1]
       z[0] = re * tr - im * ti;
       z[1] = re * ti + im * tr;
     }
@@ -111,7 +136,7 @@ template <typename T>
 __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtSpace<T> a1, int r, int s, int cc) {
   const SrhtSpace<T>& a = blockIdx.y ? a1 : a0;
   const int N1 = a.N1, N2 = a.N2;
-  const int k1 = blockIdx.x;
+  const int k1 = xcd_logical(blockIdx.x, gridDim.x);  // neighbouring k1 share cache lines of Z
   if (a.n == 0 || k1 >= N1) return;
   const int j0 = a.soff[k1], j1 = a.soff[k1 + 1];
   if (j0 == j1) return;  // uniform: no sampled frequency has this residue
@@ -119,28 +144,48 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
   extern __shared__ double sm[];
   double* wN2 = sm;               // 2 N2
   double* Zs = wN2 + 2 * N2;      // 2 cc N2
-  double* red = Zs + 2 * cc * N2; // (S2T / 64) 2 CC2MAX
   for (int j = tid; j < N2; j += S2T) twiddle(j, N2, wN2[2 * j], wN2[2 * j + 1]);
   const double scale = sqrt(2.0 / (double)s);  // sqrt(n / s) times the DCT's sqrt(2 / n)
   for (int c0 = 0; c0 < r; c0 += cc) {
     const int ncol = min(cc, r - c0);
     __syncthreads();
-    for (int e = tid; e < ncol * N2; e += S2T) {
-      const int cl = e / N2, bb = e % N2;
-      const double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N1 + k1) * N2 + bb);
-      Zs[2 * e] = z[0];
-      Zs[2 * e + 1] = z[1];
+    for (int e0 = 0; e0 < ncol * N2; e0 += LD * S2T) {
+      double zr[LD], zi[LD];
+#pragma unroll
+      for (int u = 0; u < LD; ++u) {
+        const int e = e0 + u * S2T + tid;
+        const int cl = e / N2, bb = e % N2;
+        zr[u] = zi[u] = 0.0;
+        if (e < ncol * N2) {
+          const double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N2 + bb) * N1 + k1);
+          zr[u] = z[0];
+          zi[u] = z[1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LD; ++u) {
+        const int e = e0 + u * S2T + tid;
+        if (e < ncol * N2) {
+          Zs[2 * e] = zr[u];
+          Zs[2 * e + 1] = zi[u];
+        }
+      }
     }
     __syncthreads();
-    for (int j = j0; j < j1; ++j) {
+    // one wavefront per sample: V_k = sum_b Z[b][k1] w_N2^{b k2}, reduced within the wavefront
+    for (int j = j0 + wv; j < j1; j += S2T / 64) {
       const int i = a.samp[2 * j], k = a.samp[2 * j + 1];
       const int64_t k2 = k / N1;
       double acc[2 * CC2MAX];
 #pragma unroll
       for (int v = 0; v < 2 * CC2MAX; ++v) acc[v] = 0.0;
-      for (int bb = tid; bb < N2; bb += S2T) {
-        const int t = (int)(((int64_t)bb * k2) % N2);
+      // t = bb k2 mod N2, advanced by 64 k2 mod N2 per iteration
+      int t = (int)(((int64_t)lane * k2) % N2);
+      const int dt = (int)(((int64_t)64 * k2) % N2);
+      for (int bb = lane; bb < N2; bb += 64) {
         const double wr = wN2[2 * t], wi = wN2[2 * t + 1];
+        t += dt;
+        if (t >= N2) t -= N2;
 #pragma unroll
         for (int cl = 0; cl < CC2MAX; ++cl) {
           if (cl < ncol) {
@@ -150,26 +195,16 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
           }
         }
       }
+      double sn, cs;  // DCT2_k = Re(exp(-i pi k / (2n)) V_k)
+      sincospi((double)k / (2.0 * (double)a.n), &sn, &cs);
+      const double ck = (k == 0) ? 0.70710678118654752440 : 1.0;
 #pragma unroll
-      for (int v = 0; v < 2 * CC2MAX; ++v) {
-        if (v < 2 * ncol) {  // uniform
-          const double x = wave_sum(acc[v]);
-          if (lane == 0) red[wv * 2 * CC2MAX + v] = x;
+      for (int cl = 0; cl < CC2MAX; ++cl) {
+        if (cl < ncol) {  // uniform
+          const double vr = wave_sum(acc[2 * cl]), vi = wave_sum(acc[2 * cl + 1]);
+          if (lane == 0) a.wraw[(int64_t)i * r + c0 + cl] = scale * ck * (vr * cs + vi * sn);
         }
       }
-      __syncthreads();
-      if (tid < ncol) {
-        double vr = 0.0, vi = 0.0;
-        for (int q = 0; q < S2T / 64; ++q) {
-          vr += red[q * 2 * CC2MAX + 2 * tid];
-          vi += red[q * 2 * CC2MAX + 2 * tid + 1];
-        }
-        double sn, cs;  // DCT2_k = Re(exp(-i pi k / (2n)) V_k)
-        sincospi((double)k / (2.0 * (double)a.n), &sn, &cs);
-        const double ck = (k == 0) ? 0.70710678118654752440 : 1.0;
-        a.wraw[(int64_t)i * r + c0 + tid] = scale * ck * (vr * cs + vi * sn);
-      }
-      __syncthreads();  // red is reused by the next sample
     }
   }
 }
@@ -281,14 +316,13 @@ void launch_srht(int r, int s, const SrhtSpace<T>& a, const SrhtSpace<T>& b, int
     maxPQ = std::max(maxPQ, sp[q]->P + sp[q]->Q);
   }
   const size_t budget = std::min<size_t>(lds_limit, 160 * 1024) - 1024;
-  // stage 1: tables 2 (N1 + P + Q) doubles, 3 cc N1 doubles per column chunk
-  const size_t tab1 = (size_t)2 * (maxN1 + maxPQ) * sizeof(double);
+  // stage 1: tables 2 (N1 + 2 (P + Q)) doubles, 3 cc N1 doubles per column chunk
+  const size_t tab1 = (size_t)2 * (maxN1 + 2 * maxPQ) * sizeof(double);
   SKR_REQUIRE(tab1 + (size_t)3 * maxN1 * sizeof(double) <= budget, "DCT embedding: N1 too large for LDS");
   const int cc1 = (int)std::min<size_t>(r, (budget - tab1) / ((size_t)3 * maxN1 * sizeof(double)));
   const size_t lds1 = tab1 + (size_t)3 * cc1 * maxN1 * sizeof(double);
-  // stage 2: twiddles 2 N2, 2 cc N2 per column chunk, the reduction buffer
-  const size_t red = (size_t)(S2T / 64) * 2 * CC2MAX * sizeof(double);
-  const size_t tab2 = (size_t)2 * maxN2 * sizeof(double) + red;
+  // stage 2: twiddles 2 N2, 2 cc N2 per column chunk
+  const size_t tab2 = (size_t)2 * maxN2 * sizeof(double);
   SKR_REQUIRE(tab2 + (size_t)2 * maxN2 * sizeof(double) <= budget, "DCT embedding: N2 too large for LDS");
   const int cc2 = (int)std::min<size_t>(std::min(r, CC2MAX), (budget - tab2) / ((size_t)2 * maxN2 * sizeof(double)));
   const size_t lds2 = tab2 + (size_t)2 * cc2 * maxN2 * sizeof(double);
