@@ -1,5 +1,6 @@
 // Subsampled randomized DCT embedding on the device: stage 1 (length-N1 DFTs in LDS, one
-// workgroup per b < N2), stage 2 (the sampled outputs, one workgroup per residue k1 = k mod N1),
+// workgroup per tile of consecutive b < N2), stage 2 (the sampled outputs, one workgroup per
+// residue k1 = k mod N1, one wavefront per sampled frequency),
 // and the pending right factor.  Host side: the factorisation n = N1 N2, N1 = P Q and the
 // sampled rows, cached per (n, s, seed).
 #include <algorithm>
@@ -21,6 +22,8 @@ constexpr int N1MAX = 3072;   // stage-1 sequence length (LDS: tables + one colu
 constexpr int N2MAX = 4096;   // stage-2 sequence length (LDS: twiddles + one column)
 constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
 constexpr int LD = 8;         // global loads in flight per thread in the staging loops
+constexpr int S1B = 8;        // widest tile of b per stage-1 workgroup
+constexpr size_t S1_SHARE = 52 * 1024;  // stage-1 LDS that leaves room for three workgroups per CU
 
 __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -36,86 +39,101 @@ __device__ inline void twiddle(int64_t t, int64_t N, double& re, double& im) {
   im = -sn;
 }
 
+// One workgroup per tile of B consecutive b: the B cc sequences of a column chunk are
+// transformed together, so that the Z entries of a tile (consecutive b for one k1) are
+// written by one workgroup.  Complex arrays in LDS are planar (real and imaginary parts in
+// separate arrays) and sequences are laid out with an odd stride, to spread LDS banks.
 template <typename T>
-__global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtSpace<T> a1, int r, int cc) {
+__global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtSpace<T> a1, int r, int cc, int B) {
   const SrhtSpace<T>& a = blockIdx.y ? a1 : a0;
   const int N1 = a.N1, N2 = a.N2, P = a.P, Q = a.Q;
-  const int b = xcd_logical(blockIdx.x, gridDim.x);  // neighbouring b share cache lines of U
-  if (a.n == 0 || b >= N2) return;                   // uniform over the workgroup
+  const int L = N1 | 1;                                   // sequence stride in LDS (odd)
+  const int b0 = xcd_logical(blockIdx.x, gridDim.x) * B;  // neighbouring tiles share cache lines of U
+  if (a.n == 0 || b0 >= N2) return;                       // uniform over the workgroup
+  const int nb = min(B, N2 - b0);
   const int tid = threadIdx.x;
   extern __shared__ double sm[];
-  double* wN1 = sm;              // 2 N1
-  double* wP = wN1 + 2 * N1;     // 2 P
-  double* wQ = wP + 2 * P;       // 2 Q
-  double* bP = wQ + 2 * Q;       // 2 P: w_n^{b k1a}
-  double* bQ = bP + 2 * P;       // 2 Q: w_n^{b P k1b}
-  double* Ts = bQ + 2 * Q;       // 2 cc N1
-  double* xs = Ts + 2 * cc * N1; // cc N1
+  double* wN1r = sm;                 // N1 each: w_N1^j
+  double* wN1i = wN1r + N1;
+  double* wPr = wN1i + N1;           // P each
+  double* wPi = wPr + P;
+  double* wQr = wPi + P;             // Q each
+  double* wQi = wQr + Q;
+  double* bPr = wQi + Q;             // B P each: w_n^{b k1a}
+  double* bPi = bPr + B * P;
+  double* bQr = bPi + B * P;         // B Q each: w_n^{b P k1b}
+  double* bQi = bQr + B * Q;
+  double* Tr = bQi + B * Q;          // B cc L each
+  double* Ti = Tr + B * cc * L;
+  double* xs = Ti + B * cc * L;      // B cc L
   const int64_t n = a.n, h = (n + 1) / 2;
-  for (int j = tid; j < N1; j += S1T) twiddle(j, N1, wN1[2 * j], wN1[2 * j + 1]);
-  for (int j = tid; j < P; j += S1T) {
-    twiddle(j, P, wP[2 * j], wP[2 * j + 1]);
-    twiddle(((int64_t)b * j) % n, n, bP[2 * j], bP[2 * j + 1]);
+  for (int j = tid; j < N1; j += S1T) twiddle(j, N1, wN1r[j], wN1i[j]);
+  for (int j = tid; j < P; j += S1T) twiddle(j, P, wPr[j], wPi[j]);
+  for (int j = tid; j < Q; j += S1T) twiddle(j, Q, wQr[j], wQi[j]);
+  for (int e = tid; e < nb * P; e += S1T) {
+    const int bi = e / P, j = e % P;
+    twiddle(((int64_t)(b0 + bi) * j) % n, n, bPr[e], bPi[e]);
   }
-  for (int j = tid; j < Q; j += S1T) {
-    twiddle(j, Q, wQ[2 * j], wQ[2 * j + 1]);
-    twiddle(((int64_t)b * P * j) % n, n, bQ[2 * j], bQ[2 * j + 1]);
+  for (int e = tid; e < nb * Q; e += S1T) {
+    const int bi = e / Q, j = e % Q;
+    twiddle(((int64_t)(b0 + bi) * P * j) % n, n, bQr[e], bQi[e]);
   }
   for (int c0 = 0; c0 < r; c0 += cc) {
     const int ncol = min(cc, r - c0);
-    __syncthreads();  // tables written, previous chunk consumed
+    const int nseq = nb * ncol;  // sequence q = bi ncol + cl
+    __syncthreads();             // tables written, previous chunk consumed
     // v[N2 a + b] with v the even entries of y = E x followed by the odd ones reversed;
     // LD loads per thread are issued before any of them is used
-    for (int e0 = 0; e0 < N1 * ncol; e0 += LD * S1T) {
+    for (int e0 = 0; e0 < N1 * nseq; e0 += LD * S1T) {
       double val[LD];
       int64_t rows[LD];
 #pragma unroll
       for (int u = 0; u < LD; ++u) {
         const int e = e0 + u * S1T + tid;
-        const int aa = e / ncol, cl = e % ncol;
-        const int64_t m = (int64_t)N2 * aa + b;
+        const int aa = e / nseq, q = e % nseq, bi = q / ncol, cl = q % ncol;
+        const int64_t m = (int64_t)N2 * aa + b0 + bi;
         rows[u] = m < h ? 2 * m : 2 * (n - 1 - m) + 1;
-        val[u] = e < N1 * ncol ? static_cast<double>(a.U[rows[u] * r + c0 + cl]) : 0.0;
+        val[u] = e < N1 * nseq ? static_cast<double>(a.U[rows[u] * r + c0 + cl]) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < LD; ++u) {
         const int e = e0 + u * S1T + tid;
-        if (e < N1 * ncol) {
-          const int aa = e / ncol, cl = e % ncol;
+        if (e < N1 * nseq) {
+          const int aa = e / nseq, q = e % nseq;
           const double sg = (splitmix_mix(a.seed + (uint64_t)(rows[u] + 1) * GOLDEN) & 1ull) ? -1.0 : 1.0;
-          xs[cl * N1 + aa] = sg * val[u];
+          xs[q * L + aa] = sg * val[u];
         }
       }
     }
     __syncthreads();
     // P-point DFTs over a1 (a = Q a1 + a2), times w_N1^{a2 k1a}
-    for (int e = tid; e < ncol * N1; e += S1T) {
-      const int cl = e / N1, rem = e % N1, k1a = rem / Q, a2 = rem % Q;
-      const double* xc = xs + cl * N1 + a2;
+    for (int e = tid; e < nseq * N1; e += S1T) {
+      const int q = e / N1, rem = e % N1, k1a = rem / Q, a2 = rem % Q;
+      const double* xc = xs + q * L + a2;
       double re = 0.0, im = 0.0;
       int idx = 0;
       for (int a1 = 0; a1 < P; ++a1) {
         const double x = xc[Q * a1];
-        re += x * wP[2 * idx];
-        im += x * wP[2 * idx + 1];
+        re += x * wPr[idx];
+        im += x * wPi[idx];
         idx += k1a;
         if (idx >= P) idx -= P;
       }
-      const int t = a2 * k1a;  // < (Q - 1)(P - 1) + 1 <= N1
-      const double tr = wN1[2 * t], ti = wN1[2 * t + 1];
-      Ts[2 * (cl * N1 + rem)] = re * tr - im * ti;
-      Ts[2 * (cl * N1 + rem) + 1] = re * ti + im * tr;
+      const int t = a2 * k1a;  // <= (Q - 1)(P - 1) < N1
+      const double tr = wN1r[t], ti = wN1i[t];
+      Tr[q * L + rem] = re * tr - im * ti;
+      Ti[q * L + rem] = re * ti + im * tr;
     }
     __syncthreads();
     // Q-point DFTs over a2: k1 = k1a + P k1b; times w_n^{b k1}
-    for (int e = tid; e < ncol * N1; e += S1T) {
-      const int cl = e / N1, rem = e % N1, k1a = rem / Q, k1b = rem % Q;
-      const double* tc = Ts + 2 * (cl * N1 + k1a * Q);
+    for (int e = tid; e < nseq * N1; e += S1T) {
+      const int q = e / N1, rem = e % N1, k1a = rem / Q, k1b = rem % Q, bi = q / ncol, cl = q % ncol;
+      const int base = q * L + k1a * Q;
       double re = 0.0, im = 0.0;
       int idx = 0;
       for (int a2 = 0; a2 < Q; ++a2) {
-        const double xr = tc[2 * a2], xi = tc[2 * a2 + 1];
-        const double wr = wQ[2 * idx], wi = wQ[2 * idx + 1];
+        const double xr = Tr[base + a2], xi = Ti[base + a2];
+        const double wr = wQr[idx], wi = wQi[idx];
         re += xr * wr - xi * wi;
         im += xr * wi + xi * wr;
         idx += k1b;
@@ -123,9 +141,10 @@ __global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtS
       }
       const int k1 = k1a + P * k1b;
       // w_n^{b k1} = w_n^{b k1a} w_n^{b P k1b}
-      const double ur = bP[2 * k1a], ui = bP[2 * k1a + 1], vr = bQ[2 * k1b], vi = bQ[2 * k1b + 1];
+      const double ur = bPr[bi * P + k1a], ui = bPi[bi * P + k1a];
+      const double vr = bQr[bi * Q + k1b], vi = bQi[bi * Q + k1b];
       const double tr = ur * vr - ui * vi, ti = ur * vi + ui * vr;
-      double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N2 + b) * N1 + k1);  // [column][b][k1]
+      double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N1 + k1) * N2 + b0 + bi);  // [column][k1][b]
       z[0] = re * tr - im * ti;
       z[1] = re * ti + im * tr;
     }
@@ -136,15 +155,17 @@ template <typename T>
 __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtSpace<T> a1, int r, int s, int cc) {
   const SrhtSpace<T>& a = blockIdx.y ? a1 : a0;
   const int N1 = a.N1, N2 = a.N2;
-  const int k1 = xcd_logical(blockIdx.x, gridDim.x);  // neighbouring k1 share cache lines of Z
+  const int k1 = blockIdx.x;
   if (a.n == 0 || k1 >= N1) return;
   const int j0 = a.soff[k1], j1 = a.soff[k1 + 1];
   if (j0 == j1) return;  // uniform: no sampled frequency has this residue
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   extern __shared__ double sm[];
-  double* wN2 = sm;               // 2 N2
-  double* Zs = wN2 + 2 * N2;      // 2 cc N2
-  for (int j = tid; j < N2; j += S2T) twiddle(j, N2, wN2[2 * j], wN2[2 * j + 1]);
+  double* wr2 = sm;              // N2 each: w_N2^j
+  double* wi2 = wr2 + N2;
+  double* Zr = wi2 + N2;         // cc N2 each
+  double* Zi = Zr + cc * N2;
+  for (int j = tid; j < N2; j += S2T) twiddle(j, N2, wr2[j], wi2[j]);
   const double scale = sqrt(2.0 / (double)s);  // sqrt(n / s) times the DCT's sqrt(2 / n)
   for (int c0 = 0; c0 < r; c0 += cc) {
     const int ncol = min(cc, r - c0);
@@ -157,7 +178,7 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
         const int cl = e / N2, bb = e % N2;
         zr[u] = zi[u] = 0.0;
         if (e < ncol * N2) {
-          const double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N2 + bb) * N1 + k1);
+          const double* z = a.Z + 2 * (((int64_t)(c0 + cl) * N1 + k1) * N2 + bb);
           zr[u] = z[0];
           zi[u] = z[1];
         }
@@ -166,34 +187,35 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
       for (int u = 0; u < LD; ++u) {
         const int e = e0 + u * S2T + tid;
         if (e < ncol * N2) {
-          Zs[2 * e] = zr[u];
-          Zs[2 * e + 1] = zi[u];
+          Zr[e] = zr[u];
+          Zi[e] = zi[u];
         }
       }
     }
     __syncthreads();
-    // one wavefront per sample: V_k = sum_b Z[b][k1] w_N2^{b k2}, reduced within the wavefront
+    // one wavefront per sample: V_k = sum_b Z[k1][b] w_N2^{b k2}, reduced within the wavefront;
+    // lane l takes b = l, l + 64, .., its twiddle advanced by the factor w_N2^{64 k2}
     for (int j = j0 + wv; j < j1; j += S2T / 64) {
       const int i = a.samp[2 * j], k = a.samp[2 * j + 1];
       const int64_t k2 = k / N1;
       double acc[2 * CC2MAX];
 #pragma unroll
       for (int v = 0; v < 2 * CC2MAX; ++v) acc[v] = 0.0;
-      // t = bb k2 mod N2, advanced by 64 k2 mod N2 per iteration
-      int t = (int)(((int64_t)lane * k2) % N2);
-      const int dt = (int)(((int64_t)64 * k2) % N2);
+      const int t0 = (int)(((int64_t)lane * k2) % N2), ts = (int)(((int64_t)64 * k2) % N2);
+      double wr = wr2[t0], wi = wi2[t0];
+      const double sr = wr2[ts], si = wi2[ts];
       for (int bb = lane; bb < N2; bb += 64) {
-        const double wr = wN2[2 * t], wi = wN2[2 * t + 1];
-        t += dt;
-        if (t >= N2) t -= N2;
 #pragma unroll
         for (int cl = 0; cl < CC2MAX; ++cl) {
           if (cl < ncol) {
-            const double zr = Zs[2 * (cl * N2 + bb)], zi = Zs[2 * (cl * N2 + bb) + 1];
+            const double zr = Zr[cl * N2 + bb], zi = Zi[cl * N2 + bb];
             acc[2 * cl] += zr * wr - zi * wi;
             acc[2 * cl + 1] += zr * wi + zi * wr;
           }
         }
+        const double nr = wr * sr - wi * si;
+        wi = wr * si + wi * sr;
+        wr = nr;
       }
       double sn, cs;  // DCT2_k = Re(exp(-i pi k / (2n)) V_k)
       sincospi((double)k / (2.0 * (double)a.n), &sn, &cs);
@@ -316,11 +338,20 @@ void launch_srht(int r, int s, const SrhtSpace<T>& a, const SrhtSpace<T>& b, int
     maxPQ = std::max(maxPQ, sp[q]->P + sp[q]->Q);
   }
   const size_t budget = std::min<size_t>(lds_limit, 160 * 1024) - 1024;
-  // stage 1: tables 2 (N1 + 2 (P + Q)) doubles, 3 cc N1 doubles per column chunk
-  const size_t tab1 = (size_t)2 * (maxN1 + 2 * maxPQ) * sizeof(double);
-  SKR_REQUIRE(tab1 + (size_t)3 * maxN1 * sizeof(double) <= budget, "DCT embedding: N1 too large for LDS");
-  const int cc1 = (int)std::min<size_t>(r, (budget - tab1) / ((size_t)3 * maxN1 * sizeof(double)));
-  const size_t lds1 = tab1 + (size_t)3 * cc1 * maxN1 * sizeof(double);
+  // stage 1: tables 2 (N1 + (B + 1)(P + Q)) doubles and 3 B cc L doubles per column chunk
+  // (L = N1 | 1); the widest tile of b (up to S1B) and chunk of columns that keep three
+  // workgroups on a compute unit, else one of each within the whole budget
+  const size_t L1 = (size_t)(maxN1 | 1);
+  auto tab1_of = [&](int Bt) { return (size_t)2 * (maxN1 + (size_t)(Bt + 1) * maxPQ) * sizeof(double); };
+  auto seq1 = [&](int Bt) { return (size_t)3 * Bt * L1 * sizeof(double); };
+  int B1 = S1B;
+  size_t budget1 = S1_SHARE;
+  while (B1 > 1 && tab1_of(B1) + seq1(B1) > budget1) B1 /= 2;
+  if (tab1_of(B1) + seq1(B1) > budget1) budget1 = budget;
+  const size_t tab1 = tab1_of(B1);
+  SKR_REQUIRE(tab1 + seq1(B1) <= budget, "DCT embedding: N1 too large for LDS");
+  const int cc1 = (int)std::min<size_t>(r, (budget1 - tab1) / seq1(B1));
+  const size_t lds1 = tab1 + (size_t)cc1 * seq1(B1);
   // stage 2: twiddles 2 N2, 2 cc N2 per column chunk
   const size_t tab2 = (size_t)2 * maxN2 * sizeof(double);
   SKR_REQUIRE(tab2 + (size_t)2 * maxN2 * sizeof(double) <= budget, "DCT embedding: N2 too large for LDS");
@@ -332,7 +363,7 @@ void launch_srht(int r, int s, const SrhtSpace<T>& a, const SrhtSpace<T>& b, int
                               (int)lds2));
   SrhtSpace<T> a1 = a, b1 = (nspaces == 2) ? b : a;
   if (nspaces == 1) b1.n = 0;
-  hipLaunchKernelGGL(srht_stage1_kernel<T>, dim3(maxN2, 2), dim3(S1T), lds1, st, a1, b1, r, cc1);
+  hipLaunchKernelGGL(srht_stage1_kernel<T>, dim3((maxN2 + B1 - 1) / B1, 2), dim3(S1T), lds1, st, a1, b1, r, cc1, B1);
   check_launch("srht_stage1");
   hipLaunchKernelGGL(srht_stage2_kernel<T>, dim3(maxN1, 2), dim3(S2T), lds2, st, a1, b1, r, s, cc2);
   check_launch("srht_stage2");

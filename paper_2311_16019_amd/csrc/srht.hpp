@@ -9,9 +9,9 @@
 // The DCT of each column is taken through a complex DFT of length n of the reordered
 // sequence v = (y_0, y_2, y_4, .., .., y_5, y_3, y_1) (Makhoul 1980):
 // DCT2(y)_k ~ Re(exp(-i pi k / (2n)) V_k).  With n = N1 N2 and N1 = P Q the DFT splits as
-//   stage 1 (every b < N2):  Z[b][k1] = w_n^{b k1} sum_a v[N2 a + b] w_N1^{a k1}
+//   stage 1 (every b < N2):  Z[k1][b] = w_n^{b k1} sum_a v[N2 a + b] w_N1^{a k1}
 //            (the length-N1 DFT in LDS as P-point and Q-point passes)
-//   stage 2 (sampled k only): V_k = sum_b Z[b][k mod N1] w_N2^{b (k div N1)}
+//   stage 2 (sampled k only): V_k = sum_b Z[k mod N1][b] w_N2^{b (k div N1)}
 // so only the s sampled outputs of the second stage are formed.
 #pragma once
 
@@ -39,7 +39,7 @@ SrhtPlan srht_plan(int64_t n, int s, uint64_t seed);
 template <typename T>
 struct SrhtSpace {
   const T* U;          // n x r row-major block to sketch
-  double* Z;           // workspace: r x N2 x N1 complex (interleaved re, im)
+  double* Z;           // workspace: r x N1 x N2 complex (interleaved re, im)
   const int* soff;     // device copy of SrhtPlan::soff
   const int* samp;     // device copy of SrhtPlan::samp
   double* wraw;        // s x r: S U before the pending factor
