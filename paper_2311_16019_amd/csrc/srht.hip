@@ -14,8 +14,8 @@
 namespace skr {
 namespace {
 
-constexpr int S1T = 256;      // threads of a stage-1 workgroup
-constexpr int S2T = 256;      // threads of a stage-2 workgroup
+constexpr int S1T = 512;      // threads of a stage-1 workgroup
+constexpr int S2T = 1024;     // threads of a stage-2 workgroup (one wavefront per sample)
 constexpr int CC2MAX = 8;     // columns per stage-2 chunk
 constexpr int PQMAX = 64;     // largest direct DFT length of stage 1
 constexpr int N1MAX = 3072;   // stage-1 sequence length (LDS: tables + one column)
@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtS
       const double* xc = xs + q * L + a2;
       double re = 0.0, im = 0.0;
       int idx = 0;
+#pragma unroll 4
       for (int a1 = 0; a1 < P; ++a1) {
         const double x = xc[Q * a1];
         re += x * wPr[idx];
@@ -131,6 +132,7 @@ __global__ void __launch_bounds__(S1T) srht_stage1_kernel(SrhtSpace<T> a0, SrhtS
       const int base = q * L + k1a * Q;
       double re = 0.0, im = 0.0;
       int idx = 0;
+#pragma unroll 4
       for (int a2 = 0; a2 < Q; ++a2) {
         const double xr = Tr[base + a2], xi = Ti[base + a2];
         const double wr = wQr[idx], wi = wQi[idx];
@@ -197,11 +199,11 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
     // lane l takes b = l, l + 64, .., its twiddle advanced by the factor w_N2^{64 k2}
     for (int j = j0 + wv; j < j1; j += S2T / 64) {
       const int i = a.samp[2 * j], k = a.samp[2 * j + 1];
-      const int64_t k2 = k / N1;
+      const unsigned k2 = (unsigned)(k / N1);  // < N2 <= 4096, so 64 k2 fits 32 bits
       double acc[2 * CC2MAX];
 #pragma unroll
       for (int v = 0; v < 2 * CC2MAX; ++v) acc[v] = 0.0;
-      const int t0 = (int)(((int64_t)lane * k2) % N2), ts = (int)(((int64_t)64 * k2) % N2);
+      const int t0 = (int)(((unsigned)lane * k2) % (unsigned)N2), ts = (int)((64u * k2) % (unsigned)N2);
       double wr = wr2[t0], wi = wi2[t0];
       const double sr = wr2[ts], si = wi2[ts];
       for (int bb = lane; bb < N2; bb += 64) {
