@@ -181,6 +181,7 @@ struct Space {
   DBuf<int> broken;
   DBuf<uint16_t> tab;
   DBuf<double> skt, sring;  // sketched orthogonalisation: S U~ and the ring of S U_j
+  DBuf<double> skpart2, srz2;  // its own sketch workspaces (the sketch of U~ may overlap that of U_j)
   int nring = 0;
   SrhtPlan srht;                   // DCT embedding: factorisation and sampled rows
   DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
@@ -221,6 +222,7 @@ class Solver {
     SKR_REQUIRE(p.orth == SKR_ORTH_EUCLIDEAN || p.orth == SKR_ORTH_SKETCHED,
                 "orth must be SKR_ORTH_EUCLIDEAN or SKR_ORTH_SKETCHED");
     sorth_ = p.orth == SKR_ORTH_SKETCHED;
+    resketch_ = sorth_ && sizeof(T) == sizeof(float);
     SKR_REQUIRE(!sorth_ || sketched_, "the sketched inner product needs an embedding");
     SKR_REQUIRE(p.recover == SKR_RECOVER_STORED || p.recover == SKR_RECOVER_TWO_PASS, "invalid recovery mode");
     SKR_REQUIRE(p.tol >= 0.0 && p.trunc_tol >= 0.0, "tolerances must be nonnegative");
@@ -415,6 +417,7 @@ class Solver {
     s.ell.alloc((size_t)r_ * r_);
     if (sketched_ && !srht_) s.tab.alloc((size_t)s.n * p_.zeta);
     if (sorth_) {
+      if (!srht_) s.skpart2.alloc((size_t)s.nchunk * s_ * r_);
       s.nring = p_.k + 1;
       s.skt.alloc((size_t)s_ * r_);
       s.sring.alloc((size_t)s.nring * s_ * r_);
@@ -546,6 +549,7 @@ class Solver {
     launch_sorth(r_, (int)s_, 0, 1, 0, sorth_args(sp_[0], sp_[0].ell.p, r_, 1),
                  sorth_args(sp_[1], sp_[1].ell.p, r_, 1), lyap_ ? 1 : 2, st_);
     launch_cgs_pass2<T>(r_, 0, a[0], a[1], st_);  // U_1 = U~ ell^{-1}
+    if (resketch_) sketch(1, st_);  // the whitening takes S U_1 of the stored (rounded) block
     whiten(0, 0, st_);
     rhs_block();
   }
@@ -558,6 +562,7 @@ class Solver {
       if (s.n == 0) continue;
       s.srht = srht_plan(s.n, (int)s_, seeds[q]);
       s.srz.alloc(srht_z_doubles(s.n, r_));
+      if (sorth_) s.srz2.alloc(srht_z_doubles(s.n, r_));
       s.srraw.alloc((size_t)s_ * r_);
       s.sroff.alloc(s.srht.soff.size());
       s.srsamp.alloc(s.srht.samp.size());
@@ -568,10 +573,10 @@ class Solver {
     }
   }
 
-  SrhtSpace<T> srht_args(Space<T>& s, const T* U, double* w, const double* pend) {
+  SrhtSpace<T> srht_args(Space<T>& s, const T* U, double* w, const double* pend, bool second_ws = false) {
     SrhtSpace<T> a{};
     a.U = U;
-    a.Z = s.srz.p;
+    a.Z = second_ws ? s.srz2.p : s.srz.p;
     a.soff = s.sroff.p;
     a.samp = s.srsamp.p;
     a.wraw = pend ? s.srraw.p : w;
@@ -587,18 +592,19 @@ class Solver {
   }
 
   SorthSpace sorth_args(Space<T>& s, double* H, int ldh, int j) {
-    return SorthSpace{s.skt.p, s.sring.p, s.nring, s.wbuf(j), s.cgs.p + cgs_coef_offset(), H, ldh, s.broken.p};
+    return SorthSpace{s.skt.p, s.sring.p, s.nring, resketch_ ? nullptr : s.wbuf(j), s.cgs.p + cgs_coef_offset(), H,
+                      ldh, s.broken.p};
   }
 
-  // w = S U~ for the block in the work buffer (both spaces)
+  // w = S U~ for the block in the work buffer (both spaces), in workspaces of its own
   void sketch_work(hipStream_t st) {
     if (srht_) {
-      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].work.p, sp_[0].skt.p, nullptr),
-                     srht_args(sp_[1], sp_[1].work.p, sp_[1].skt.p, nullptr), lyap_ ? 1 : 2, lds_limit_, st);
+      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].work.p, sp_[0].skt.p, nullptr, true),
+                     srht_args(sp_[1], sp_[1].work.p, sp_[1].skt.p, nullptr, true), lyap_ ? 1 : 2, lds_limit_, st);
       return;
     }
-    SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk};
-    SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk};
+    SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart2.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk};
+    SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart2.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk};
     launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, nullptr, nullptr, lds_limit_, st);
   }
 
@@ -647,16 +653,18 @@ class Solver {
   void sketch(int j, hipStream_t s) {
     if (srht_) {
       const size_t off = (size_t)j * r_ * r_;
-      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].slot(j), sp_[0].wbuf(j), fast_ ? sp_[0].Pall.p + off : nullptr),
-                     srht_args(sp_[1], sp_[1].slot(j), sp_[1].wbuf(j), fast_ ? sp_[1].Pall.p + off : nullptr),
+      const bool pend = fast_ && !sorth_;  // the sketched-inner-product step stores final blocks
+      launch_srht<T>(r_, (int)s_, srht_args(sp_[0], sp_[0].slot(j), sp_[0].wbuf(j), pend ? sp_[0].Pall.p + off : nullptr),
+                     srht_args(sp_[1], sp_[1].slot(j), sp_[1].wbuf(j), pend ? sp_[1].Pall.p + off : nullptr),
                      lyap_ ? 1 : 2, lds_limit_, s);
       return;
     }
     SketchSpace<T> k0{sp_[0].slot(j), sp_[0].tab.p, sp_[0].skpart.p, sp_[0].wbuf(j), sp_[0].n, sp_[0].nchunk};
     SketchSpace<T> k1{sp_[1].slot(j), sp_[1].tab.p, sp_[1].skpart.p, sp_[1].wbuf(j), sp_[1].n, sp_[1].nchunk};
     const size_t off = (size_t)j * r_ * r_;
-    launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, fast_ ? sp_[0].Pall.p + off : nullptr,
-                             fast_ ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
+    const bool pend = fast_ && !sorth_;  // the sketched-inner-product step stores final blocks
+    launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, pend ? sp_[0].Pall.p + off : nullptr,
+                             pend ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
   }
 
   void whiten(int d, int step, hipStream_t s) {
@@ -716,6 +724,10 @@ class Solver {
     launch_sorth(r_, (int)s_, nw, i0, d, sorth_args(sp_[0], sp_[0].H.p, ld_, d + 1),
                  sorth_args(sp_[1], sp_[1].H.p, ld_, d + 1), lyap_ ? 1 : 2, st_);
     prof_.end();
+    if (resketch_ && !sp_[0].stored) {
+      // ring buffer: slot(d+1) held U_{d+1-nslots}, whose sketch runs on the auxiliary stream
+      SKR_HIP(hipStreamWaitEvent(st_, ev_sketch_, 0));
+    }
     prof_.begin(KF_UPDATE);
     launch_cgs_pass2<T>(r_, nw, a[0], a[1], st_);
     prof_.end();
@@ -726,7 +738,7 @@ class Solver {
   // with the next block step; the sketch of block d + 2 overlaps this whitening.
   void after_step(int d) {
     if (!sketched_) return;  // t-PKSM: no embedding
-    if (sorth_) {  // S U_{d+1} is already in wbuf(d + 1)
+    if (sorth_ && !resketch_) {  // S U_{d+1} is already in wbuf(d + 1)
       SKR_HIP(hipEventRecord(ev_block_, st_));
       SKR_HIP(hipStreamWaitEvent(aux2_, ev_block_, 0));
       prof_.begin(KF_WHITEN, aux2_);
@@ -892,6 +904,10 @@ class Solver {
   bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
   bool lyap_ = false;      // A X + X A^T = C1 C1^T on one Krylov space
   bool sorth_ = false;     // truncated orthogonalisation in the sketched inner product
+  // ... whose whitening takes the sketch of the stored block rather than the sketch-space
+  // S U_{d+1}: with an FP32 basis the two differ by the rounding of the stored block, and
+  // the sketched QR must describe the basis that the recovery uses
+  bool resketch_ = false;
   bool srht_ = false;      // subsampled randomized DCT embedding instead of the sparse sign one
   skr_params p_;
   hipStream_t st_;

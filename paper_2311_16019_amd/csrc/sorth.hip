@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(ST) sorth_kernel(SorthSpace a0, SorthSpace a1,
     load_row<double, R>(w, i, x);
     times_upper<R>(x, RFi, y);
     store_row<double, R>(out, i, y);
-    store_row<double, R>(a.wout, i, y);
+    if (a.wout) store_row<double, R>(a.wout, i, y);
   }
   // coefficients of U_{d+1} = U~ R^{-1} - sum_i U_i (h_i R^{-1}); all zero after a breakdown
   for (int e = tid; e < (nw + 1) * RR; e += ST) {

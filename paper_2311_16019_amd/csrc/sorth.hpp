@@ -21,7 +21,8 @@ struct SorthSpace {
   double* w;        // s x r row-major: S U~ on entry, overwritten
   double* ring;     // nring slots of s x r: S U_j in slot j % nring
   int nring;
-  double* wout;     // s x r: copy of S U_{d+1} for the sketched QR update (which overwrites it)
+  double* wout;     // s x r: copy of S U_{d+1} for the sketched QR update (which overwrites it),
+                    // or null when the update takes a sketch of the stored block instead
   double* coef;     // [R^{-1} | h_{i0} R^{-1} | ..] r x r row-major each, read by the update pass
   double* H;        // column-major, leading dimension ldh; for the start block its R factor
   int ldh;
