@@ -1,6 +1,6 @@
 """GPU (gfx950) parity of the HIP library against the FP64 oracle, through the C ABI.
 
-Both sides run on the same seeded inputs with the same embedding seed.  Parity is judged
+Both sides run on the same seeded inputs with the same embedding seed.  Parity is measured
 on what is unique: the product X1 X2^T (the factors are unique only up to an invertible
 ell x ell transformation) and the residual estimates.  Fixed-d runs (tol = 0) keep the
 stopping step identical on both sides.  Bars: relative product distance <= 1e-6 (FP64
