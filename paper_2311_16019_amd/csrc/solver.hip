@@ -182,6 +182,7 @@ struct Space {
   DBuf<uint16_t> tab;
   DBuf<double> skt, sring;  // sketched orthogonalisation: S U~ and the ring of S U_j
   DBuf<double> skpart2, srz2;  // its own sketch workspaces (the sketch of U~ may overlap that of U_j)
+  DBuf<double> sopart, sostate;  // partial sums and small state of its sketch-space launches
   int nring = 0;
   SrhtPlan srht;                   // DCT embedding: factorisation and sampled rows
   DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
@@ -419,6 +420,8 @@ class Solver {
     if (sorth_) {
       if (!srht_) s.skpart2.alloc((size_t)s.nchunk * s_ * r_);
       s.nring = p_.k + 1;
+      s.sopart.alloc(sorth_part_doubles());
+      s.sostate.alloc(sorth_state_doubles());
       s.skt.alloc((size_t)s_ * r_);
       s.sring.alloc((size_t)s.nring * s_ * r_);
     }
@@ -592,8 +595,8 @@ class Solver {
   }
 
   SorthSpace sorth_args(Space<T>& s, double* H, int ldh, int j) {
-    return SorthSpace{s.skt.p, s.sring.p, s.nring, resketch_ ? nullptr : s.wbuf(j), s.cgs.p + cgs_coef_offset(), H,
-                      ldh, s.broken.p};
+    return SorthSpace{s.skt.p,  s.sring.p, s.nring,    resketch_ ? nullptr : s.wbuf(j), s.cgs.p + cgs_coef_offset(),
+                      H,        ldh,       s.broken.p, s.sopart.p,                      s.sostate.p};
   }
 
   // w = S U~ for the block in the work buffer (both spaces), in workspaces of its own

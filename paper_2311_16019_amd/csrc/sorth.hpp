@@ -27,10 +27,16 @@ struct SorthSpace {
   double* H;        // column-major, leading dimension ldh; for the start block its R factor
   int ldh;
   int* broken;      // first step at which the space broke down (INT_MAX if none)
+  double* part;     // sorth_part_doubles(): per-workgroup partial sums (two sets, alternating)
+  double* state;    // sorth_state_doubles(): coefficients and factors passed between launches
 };
 
+int sorth_groups(int s);          // workgroups per space of each launch
+size_t sorth_part_doubles();
+size_t sorth_state_doubles();
+
 // Block step d (d = 0: the start block, nw = 0) on the window i0 .. i0 + nw - 1 (nw <= 3,
-// r <= 4); one workgroup per space, both spaces in one launch or only `a` when nspaces is 1.
+// r <= 4): nw + 3 launches, each over both spaces or only `a` when nspaces is 1.
 void launch_sorth(int r, int s, int nw, int i0, int d, const SorthSpace& a, const SorthSpace& b, int nspaces,
                   hipStream_t st);
 
