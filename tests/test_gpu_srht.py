@@ -111,3 +111,34 @@ def test_srht_full_size_convdiff_fixed_d():
         dist = product_distance(g, o)
         assert dist <= TOL[precision][0], (precision, dist)
         assert history_ratio(g, o) <= TOL[precision][1]
+
+
+def test_srht_prime_size_and_wide_block():
+    """Degenerate and chunked plans: a prime n (no split, N1 = 1: stage 1 is the reordering
+    and stage 2 sums the whole length-n DFT per sampled row) and r = 8 (the general block
+    step, columns of the sampled stage processed in chunks)."""
+    import scipy.sparse as sp
+    from workloads.stencil import CSR
+    n = 1021
+    rng = np.random.Generator(np.random.PCG64(11))
+    off = -np.ones(n - 1)
+    A = CSR.from_scipy(sp.diags([off, np.full(n, 4.0), off], [-1, 0, 1]).tocsr())
+    B = CSR.from_scipy(sp.diags([0.5 * off, np.full(n, 3.0), off], [-1, 0, 1]).tocsr())
+    cfg = dict(A=A, B=B, sigma=None, C1=rng.standard_normal((n, 2)), C2=rng.standard_normal((n, 2)))
+    prm = dict(k=2, maxit=8, p=4, s=200, tol=0.0, seed=4030)
+    for precision in ("fp64", "mixed"):
+        print(f"srht prime n=1021 {precision}", flush=True)
+        g, _ = gpu_solve(cfg, precision=precision, sketch="srht", **prm)
+        o = oracle_solve(cfg, sketch="srht", **prm)
+        assert g.iters == o.d == prm["maxit"]
+        assert product_distance(g, o) <= TOL[precision][0]
+        assert history_ratio(g, o) <= TOL[precision][1]
+    cfg = make_config("aniso3d_100", m=11, r=8)
+    prm = dict(k=2, maxit=10, p=5, s=880, tol=0.0, seed=4031)
+    for precision in ("fp64", "mixed"):
+        print(f"srht aniso3d m=11 r=8 {precision}", flush=True)
+        g, _ = gpu_solve(cfg, precision=precision, sketch="srht", **prm)
+        o = oracle_solve(cfg, sketch="srht", **prm)
+        assert g.iters == o.d == prm["maxit"]
+        assert product_distance(g, o) <= TOL[precision][0]
+        assert history_ratio(g, o) <= TOL[precision][1]
