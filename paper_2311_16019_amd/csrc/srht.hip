@@ -24,6 +24,7 @@ constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
 constexpr int LD = 8;         // global loads in flight per thread in the staging loops
 constexpr int S1B = 8;        // widest tile of b per stage-1 workgroup
 constexpr size_t S1_SHARE = 52 * 1024;  // stage-1 LDS that leaves room for three workgroups per CU
+constexpr size_t S2_SHARE = 80 * 1024;  // stage-2 LDS that leaves room for two workgroups per CU
 
 __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -163,11 +164,8 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
   if (j0 == j1) return;  // uniform: no sampled frequency has this residue
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   extern __shared__ double sm[];
-  double* wr2 = sm;              // N2 each: w_N2^j
-  double* wi2 = wr2 + N2;
-  double* Zr = wi2 + N2;         // cc N2 each
+  double* Zr = sm;               // cc N2 each
   double* Zi = Zr + cc * N2;
-  for (int j = tid; j < N2; j += S2T) twiddle(j, N2, wr2[j], wi2[j]);
   const double scale = sqrt(2.0 / (double)s);  // sqrt(n / s) times the DCT's sqrt(2 / n)
   for (int c0 = 0; c0 < r; c0 += cc) {
     const int ncol = min(cc, r - c0);
@@ -204,8 +202,9 @@ __global__ void __launch_bounds__(S2T) srht_stage2_kernel(SrhtSpace<T> a0, SrhtS
 #pragma unroll
       for (int v = 0; v < 2 * CC2MAX; ++v) acc[v] = 0.0;
       const int t0 = (int)(((unsigned)lane * k2) % (unsigned)N2), ts = (int)((64u * k2) % (unsigned)N2);
-      double wr = wr2[t0], wi = wi2[t0];
-      const double sr = wr2[ts], si = wi2[ts];
+      double wr, wi, sr, si;
+      twiddle(t0, N2, wr, wi);
+      twiddle(ts, N2, sr, si);
       for (int bb = lane; bb < N2; bb += 64) {
 #pragma unroll
         for (int cl = 0; cl < CC2MAX; ++cl) {
@@ -354,11 +353,13 @@ void launch_srht(int r, int s, const SrhtSpace<T>& a, const SrhtSpace<T>& b, int
   SKR_REQUIRE(tab1 + seq1(B1) <= budget, "DCT embedding: N1 too large for LDS");
   const int cc1 = (int)std::min<size_t>(r, (budget1 - tab1) / seq1(B1));
   const size_t lds1 = tab1 + (size_t)cc1 * seq1(B1);
-  // stage 2: twiddles 2 N2, 2 cc N2 per column chunk
-  const size_t tab2 = (size_t)2 * maxN2 * sizeof(double);
-  SKR_REQUIRE(tab2 + (size_t)2 * maxN2 * sizeof(double) <= budget, "DCT embedding: N2 too large for LDS");
-  const int cc2 = (int)std::min<size_t>(std::min(r, CC2MAX), (budget - tab2) / ((size_t)2 * maxN2 * sizeof(double)));
-  const size_t lds2 = tab2 + (size_t)2 * cc2 * maxN2 * sizeof(double);
+  // stage 2: 2 cc N2 doubles per column chunk, within a share that leaves room for two
+  // workgroups on a compute unit (one column at least)
+  const size_t col2 = (size_t)2 * maxN2 * sizeof(double);
+  SKR_REQUIRE(col2 <= budget, "DCT embedding: N2 too large for LDS");
+  const size_t budget2 = std::max(col2, std::min(budget, S2_SHARE));
+  const int cc2 = (int)std::min<size_t>(std::min(r, CC2MAX), budget2 / col2);
+  const size_t lds2 = (size_t)cc2 * col2;
   SKR_HIP(hipFuncSetAttribute((const void*)srht_stage1_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds1));
   SKR_HIP(hipFuncSetAttribute((const void*)srht_stage2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
