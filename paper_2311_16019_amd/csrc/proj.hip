@@ -473,17 +473,17 @@ ProjSolver::~ProjSolver() {
   if (aux_) stream_release(aux_);
 }
 
-void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar) {
+void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar, hipStream_t st) {
   const int m = d * r_, ld = sp.ld, ldm = m + r_;
   // Mbar = T_{d+1} H_d_bar  ((m + r) x m)
   if (!sp.broken) {
-    dense::gemm(false, false, m + r_, m, m + r_, 1.0, sp.T, ld, sp.H, ld, 0.0, Mbar, ldm, st_);
+    dense::gemm(false, false, m + r_, m, m + r_, 1.0, sp.T, ld, sp.H, ld, 0.0, Mbar, ldm, st);
   } else {  // h_{d+1,d} = 0: only T_d H_d, last block row zero
-    dense::set_zero(m + r_, m, Mbar, ldm, st_);
-    dense::gemm(false, false, m, m, m, 1.0, sp.T, ld, sp.H, ld, 0.0, Mbar, ldm, st_);
+    dense::set_zero(m + r_, m, Mbar, ldm, st);
+    dense::gemm(false, false, m, m, m, 1.0, sp.T, ld, sp.H, ld, 0.0, Mbar, ldm, st);
   }
   // Mbar <- Mbar T_d^{-1}
-  dense::trsm_right_upper(m + r_, m, sp.T, ld, Mbar, ldm, st_);
+  dense::trsm_right_upper(m + r_, m, sp.T, ld, Mbar, ldm, st);
 }
 
 
@@ -647,8 +647,13 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   SKR_REQUIRE(m <= mmax_, "projected size exceeds the allocation");
   m_ = m;
   const int ldm = m + r_;
-  form(d, u, mbar_u_.p);
-  form(d, v, mbar_v_.p);
+  // the two spaces' products and triangular solves (chains of small launches) concurrently
+  SKR_HIP(hipEventRecord(ev_main_, st_));
+  SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
+  form(d, u, mbar_u_.p, st_);
+  form(d, v, mbar_v_.p, aux_);
+  SKR_HIP(hipEventRecord(ev_aux_, aux_));
+  SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
   dense::copy(m, m, mbar_u_.p, ldm, a_.p, m, st_);
   dense::transpose(m, m, mbar_v_.p, ldm, b_.p, m, st_);
   hipLaunchKernelGGL(rhs_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, r_, F11,

@@ -53,7 +53,7 @@ class ProjSolver {
   const double* Y() const { return c_.p; }
 
  private:
-  void form(int d, const ProjSpace& sp, double* Mbar);
+  void form(int d, const ProjSpace& sp, double* Mbar, hipStream_t st);
   // G = Y P_-(B) for A Y + Y B = F given Al = A (ld lal), B = Mst^T (Mst ld lms), the sign
   // S of B (or of B^T when s_trans) and F from F11 (transposed when f_trans); q = rank P_-.
   void deflate_right(int m, const double* Al, int lal, const double* Mst, int lms, const double* S, int s_trans,

@@ -350,9 +350,14 @@ class Solver {
     DBuf<double> W1((size_t)m * ell), W2((size_t)m * ell);
     dense::copy(m, ell, proj.Y1(), m, W1.p, m, st_);
     dense::copy(m, ell, proj.Y2(), m, W2.p, m, st_);
-    dense::trsm_left_upper(m, ell, sp_[0].Tm.p, ld_, W1.p, m, st_);
     Space<T>& sv = lyap_ ? sp_[0] : sp_[1];  // the second space of the factors
-    dense::trsm_left_upper(m, ell, sv.Tm.p, ld_, W2.p, m, st_);
+    // the two triangular solves (chains of small launches) concurrently
+    SKR_HIP(hipEventRecord(ev_block_, st_));
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
+    dense::trsm_left_upper(m, ell, sp_[0].Tm.p, ld_, W1.p, m, st_);
+    dense::trsm_left_upper(m, ell, sv.Tm.p, ld_, W2.p, m, aux_);
+    SKR_HIP(hipEventRecord(ev_aux_done_, aux_));
+    SKR_HIP(hipStreamWaitEvent(st_, ev_aux_done_, 0));
     res->X1.alloc((size_t)sp_[0].n * ell);
     res->X2.alloc((size_t)sv.n * ell);
     if (p_.recover == SKR_RECOVER_STORED) {
