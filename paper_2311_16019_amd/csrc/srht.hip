@@ -25,6 +25,7 @@ constexpr int LD = 8;         // global loads in flight per thread in the stagin
 constexpr int S1B = 8;        // widest tile of b per stage-1 workgroup
 constexpr size_t S1_SHARE = 52 * 1024;  // stage-1 LDS that leaves room for three workgroups per CU
 constexpr size_t S2_SHARE = 80 * 1024;  // stage-2 LDS that leaves room for two workgroups per CU
+constexpr double SAMPLE_W = 4.0;        // cost of a sampled-stage multiply-add against a stage-1 one
 
 __host__ __device__ inline uint64_t splitmix_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -268,7 +269,8 @@ SrhtPlan srht_plan(int64_t n, int s, uint64_t seed) {
   pl.n = n;
   pl.s = s;
   pl.seed = seed;
-  // n = N1 N2, N1 = P Q: the cheapest split by n (P + Q) + s N2 multiply-adds per column
+  // n = N1 N2, N1 = P Q: the cheapest split by n (P + Q) + SAMPLE_W s N2 multiply-adds per
+  // column (a multiply-add of the sampled stage weighted by its measured relative cost)
   double best = -1.0;
   for (int64_t N1 = 1; N1 <= std::min<int64_t>(n, N1MAX); ++N1) {
     if (n % N1) continue;
@@ -281,7 +283,7 @@ SrhtPlan srht_plan(int64_t n, int s, uint64_t seed) {
         bq = (int)(N1 / P);
       }
     if (bp == 0) continue;
-    const double cost = (double)n * (bp + bq) + (double)s * (double)N2;
+    const double cost = (double)n * (bp + bq) + SAMPLE_W * (double)s * (double)N2;
     if (best < 0.0 || cost < best) {
       best = cost;
       pl.N1 = (int)N1;
