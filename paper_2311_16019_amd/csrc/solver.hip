@@ -249,9 +249,9 @@ class Solver {
       throw Error(SKR_ENOTSUP, "the Lyapunov solve needs stored-basis recovery");
     int dev = 0;
     SKR_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    SKR_HIP(hipGetDeviceProperties(&prop, dev));
-    lds_limit_ = std::max<size_t>(65536, prop.sharedMemPerBlock);
+    int lds = 0;  // one attribute: the whole property structure took about a millisecond per solve
+    SKR_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    lds_limit_ = std::max<size_t>(65536, (size_t)lds);
     setup(sp_[0], A, tu);
     setup(sp_[1], lyap_ ? nullptr : B, tv);
     if (srht_) setup_srht();
