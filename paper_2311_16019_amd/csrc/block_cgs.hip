@@ -189,43 +189,84 @@ __global__ void __launch_bounds__(WG) cgs_spmm_kernel(CgsPass<T> s0, CgsPass<T> 
 
 // 1b: the window products U'_i^T U~ and U~^T U~ from the stored (rounded) U~: independent
 // streaming loads, two rows per thread in flight.
+// Rows are kept in their storage type until used (half the registers in FP32), and only
+// the upper triangle of the symmetric U~^T U~ is accumulated; the products are the same
+// operations in the same order as for the full matrix, which is mirrored when the partials
+// are written.
+template <typename T, int R>
+__device__ inline void load_raw(const T* __restrict__ p, int row, T (&x)[R]) {
+  const T* q = p + (size_t)row * R;
+  if constexpr (sizeof(T) == 4 && R == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(q);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else if constexpr (sizeof(T) == 4 && R == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(q);
+    x[0] = v.x; x[1] = v.y;
+  } else if constexpr (sizeof(T) == 8 && R % 2 == 0) {
+#pragma unroll
+    for (int c = 0; c < R; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(q + c);
+      x[c] = v.x; x[c + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[c] = q[c];
+  }
+}
+
 template <typename T, int R, int NW>
 __global__ void __launch_bounds__(WG) cgs_dots_kernel(CgsPass<T> s0, CgsPass<T> s1) {
-  constexpr int RR = R * R, NV = (NW + 1) * RR;
+  constexpr int RR = R * R, NV = (NW + 1) * RR, NG = R * (R + 1) / 2;
   const Rows wi = rows_of(s0, s1);
   const CgsPass<T>& sp = wi.space ? s1 : s0;
   __shared__ double scratch[(WG / 64) * NV];
-  double acc[NV];
+  double accw[NW > 0 ? NW * RR : 1], accg[NG];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int v = 0; v < (NW > 0 ? NW * RR : 1); ++v) accw[v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NG; ++v) accg[v] = 0.0;
   for (int base = wi.row0; base < wi.row1; base += 2 * WG) {
-    double y[2][R], w[2][NW > 0 ? NW : 1][R];
+    T y[2][R], w[2][NW > 0 ? NW : 1][R];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int row = base + h * WG + threadIdx.x;
       const bool ok = row < wi.row1;
       const int rr = ok ? row : wi.row0;  // rows past the end read a valid row, weighted 0
-      load_row<T, R>(sp.Y, rr, y[h]);
+      load_raw<T, R>(sp.Y, rr, y[h]);
 #pragma unroll
-      for (int i = 0; i < NW; ++i) load_row<T, R>(sp.W[i], rr, w[h][i]);
+      for (int i = 0; i < NW; ++i) load_raw<T, R>(sp.W[i], rr, w[h][i]);
       if (!ok) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) y[h][c] = 0.0;
+        for (int c = 0; c < R; ++c) y[h][c] = T(0);
       }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      int g = 0;
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
-        for (int b = 0; b < R; ++b) acc[NW * RR + a * R + b] += y[h][a] * y[h][b];
+        for (int b = a; b < R; ++b, ++g) accg[g] += (double)y[h][a] * (double)y[h][b];
 #pragma unroll
       for (int i = 0; i < NW; ++i)
 #pragma unroll
         for (int a = 0; a < R; ++a)
 #pragma unroll
-          for (int b = 0; b < R; ++b) acc[i * RR + a * R + b] += w[h][i][a] * y[h][b];
+          for (int b = 0; b < R; ++b) accw[i * RR + a * R + b] += (double)w[h][i][a] * (double)y[h][b];
     }
+  }
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NW * RR; ++v) acc[v] = accw[v];
+  {
+    int g = 0;
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = a; b < R; ++b, ++g) {
+        acc[NW * RR + a * R + b] = accg[g];
+        acc[NW * RR + b * R + a] = accg[g];
+      }
   }
   write_partials<NV>(acc, sp.part, sp.nwg, wi.local, scratch);
 }
