@@ -231,14 +231,19 @@ def main():
         wall["grads"] += 1e3 * (t3 - t2)
         return f, a, g
 
-    # warmup with every kernel family timed: find the dominant family
-    fam_total = {}
+    # warm-up with every kernel family timed: the per-family table and the roofline kernel,
+    # the single-kernel streaming family (spmm, dots, update) with the most time.  The timed
+    # steps record events around that family's launches only (events around every launch of
+    # every family lengthen the block steps by about a fifth).
+    fam_warm = {}
     for _ in range(max(1, args.warmup)):
         f, a, _ = one_step(args.precision, profile=True)
         for res in (f, a):
             for k, (nl, ms) in res.kernels.items():
-                fam_total[k] = fam_total.get(k, 0.0) + ms
-    dominant = max(fam_total, key=fam_total.get)
+                L, M = fam_warm.get(k, (0, 0.0))
+                fam_warm[k] = (L + nl, M + ms)
+    single = [k for k in ("spmm", "dots", "update") if k in fam_warm]
+    dominant = max(single, key=lambda k: fam_warm[k][1])
 
     torch.cuda.synchronize()
     for key in wall:
@@ -249,7 +254,7 @@ def main():
     split = dict(steps=0.0, proj=0.0, recover=0.0)
     last = None
     for _ in range(args.steps):
-        f, a, g = one_step(args.precision, profile=True)
+        f, a, g = one_step(args.precision, profile=dominant)
         for res in (f, a):
             steps_done += res.iters
             split["steps"] += res.ms_steps
@@ -267,9 +272,6 @@ def main():
     f, a, g = last
     true_res = skr.true_residual(A, B, f.X1, f.X2, C1, C2)
     w = 4 if args.precision == "mixed" else 8
-    # the roofline kernel: the single-kernel streaming family with the most time
-    single = [f for f in ("spmm", "dots", "update") if f in fam]
-    dominant = max(single, key=lambda f: fam[f][1]) if single else dominant
     nl, ms = fam[dominant]
     d_avg = (win + 1) / 2.0
     per_launch = algorithmic_bytes(dominant, cfg, w, d_avg)
@@ -279,8 +281,8 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=int(rec["bytes_per_launch"]) if rec else None,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
-    families = {}
-    for k, v in fam.items():
+    families = {}  # from the warm-up step(s), every family timed
+    for k, v in fam_warm.items():
         b = algorithmic_bytes(k, cfg, w, d_avg)
         families[k] = dict(launches=v[0], avg_us=round(1000.0 * v[1] / v[0], 2))
         if b:
@@ -294,6 +296,8 @@ def main():
                                     f"{win} block steps per solve, forward + adjoint, stored-basis recovery",
                            n=cfg["n"], r=cfg["r"], k=cfg["k"], s=cfg["s"], window=win, precision=args.precision),
                roofline=roofline, kernel_families=families,
+               kernel_families_from="warm-up step, every kernel family timed (the timed steps time the roofline "
+                                    "kernel's family only)",
                block_steps_per_s=round(steps_done / (split["steps"] * 1e-3), 1),
                time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
                                   projected_solves=round(split["proj"] / args.steps, 2),

@@ -85,9 +85,12 @@ enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in 
  *             are ignored.
  *   recover   SKR_RECOVER_STORED (keep every basis block in HBM) or
  *             SKR_RECOVER_TWO_PASS (keep k+1 blocks, regenerate them for the factors)
- *   profile   nonzero: record HIP events around every launch of each kernel family of
- *             the block step (adds a few microseconds per launch); see
- *             skr_result_kernel_stats
+ *   profile   1: record HIP events around every launch of each kernel family of the block
+ *             step; 2 + f: only around the launches of family f (index f of
+ *             skr_result_kernel_stats: 0 spmm, 1 dots, 2 reduce, 3 update, 4 sketch,
+ *             5 whiten); 0: none.  Each timed launch adds two event records to its stream
+ *             (on the benchmark problem timing every family lengthens the block steps by
+ *             about a fifth; timing one family costs much less)
  *   trunc_tol relative Frobenius cutoff of the low-rank factorisation of the projected
  *             solution Y (0 keeps everything)
  *   orth      SKR_ORTH_EUCLIDEAN: the truncated block Gram-Schmidt and the QR of the new

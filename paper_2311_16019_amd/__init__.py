@@ -127,6 +127,9 @@ class Result:
     proj: dict = field(default_factory=dict)     # last projected solve: newton_iters, neg_a, neg_b, resid
 
 
+KERNEL_FAMILIES = ("spmm", "dots", "reduce", "update", "sketch", "whiten")  # skr_result_kernel_stats order
+
+
 def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64", recover="stored",
             trunc_tol=1e-12, profile=False, sketch="sparse_sign", orth="euclidean"):
     prm = _lib.Params()
@@ -138,7 +141,8 @@ def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64
     prm.sketch = {"sparse_sign": _lib.SKR_SKETCH_SPARSE_SIGN, "srht": _lib.SKR_SKETCH_SRHT,
                   "none": _lib.SKR_SKETCH_NONE}[sketch]
     prm.orth = {"euclidean": _lib.SKR_ORTH_EUCLIDEAN, "sketched": _lib.SKR_ORTH_SKETCHED}[orth]
-    prm.profile = 1 if profile else 0
+    # profile: False, True (every kernel family) or one family's name (only its launches)
+    prm.profile = (2 + KERNEL_FAMILIES.index(profile)) if isinstance(profile, str) else (1 if profile else 0)
     return prm
 
 

@@ -120,22 +120,24 @@ int step_wgs(int n) {
   return std::max(8, std::min(1024, g));
 }
 
-// HIP-event timing of kernel families on the solve's stream (enabled by params.profile).
+// HIP-event timing of kernel families on the solve's stream (params.profile: 1 times every
+// family, 2 + f only family f; each timed launch adds two event records to its stream).
 class Profiler {
  public:
-  Profiler(bool on, hipStream_t st) : on_(on), st_(st) {}
+  Profiler(int mode, hipStream_t st) : on_(mode != 0), only_(mode >= 2 ? mode - 2 : -1), st_(st) {}
   ~Profiler() {
     for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : pool_) (void)hipEventDestroy(e);
   }
   void begin(int fam, hipStream_t s = nullptr) {
-    if (!on_) return;
+    active_ = on_ && (only_ < 0 || fam == only_);
+    if (!active_) return;
     cur_ = {get(), nullptr, fam};
     cur_st_ = s ? s : st_;
     SKR_HIP(hipEventRecord(cur_.a, cur_st_));
   }
   void end() {
-    if (!on_) return;
+    if (!active_) return;
     cur_.b = get();
     SKR_HIP(hipEventRecord(cur_.b, cur_st_));
     pending_.push_back(cur_);
@@ -161,7 +163,8 @@ class Profiler {
     SKR_HIP(hipEventCreate(&e));
     return e;
   }
-  bool on_;
+  bool on_, active_ = false;
+  int only_;
   hipStream_t st_, cur_st_ = nullptr;
   Pair cur_{};
   std::vector<Pair> pending_;
@@ -203,7 +206,7 @@ class Solver {
   // B == nullptr: the Lyapunov specialisation A X + X A^T = C1 C1^T (one Krylov space; the
   // second space is an empty placeholder that the tandem kernels skip).
   Solver(const skr_op_s* A, int tu, const skr_op_s* B, int tv, int r, const skr_params& p, hipStream_t st)
-      : r_(r), p_(p), st_(st), prof_(p.profile != 0, st) {
+      : r_(r), p_(p), st_(st), prof_(p.profile, st) {
     lyap_ = (B == nullptr);
     aux_ = stream_acquire();
     aux2_ = stream_acquire();
@@ -214,6 +217,7 @@ class Solver {
     SKR_REQUIRE(r >= 1 && r <= RMAX, "r must be in [1, 16]");
     SKR_REQUIRE(p.k >= 1, "k must be >= 1");
     SKR_REQUIRE(p.maxit >= 1, "maxit must be >= 1");
+    SKR_REQUIRE(p.profile >= 0 && p.profile < 2 + KF_COUNT, "profile must be 0, 1 or 2 + a kernel family index");
     SKR_REQUIRE(p.p >= 1, "p must be >= 1");
     SKR_REQUIRE(p.zeta >= 1 && p.zeta <= 64, "zeta must be in [1, 64]");
     SKR_REQUIRE(p.sketch == SKR_SKETCH_SPARSE_SIGN || p.sketch == SKR_SKETCH_SRHT || p.sketch == SKR_SKETCH_NONE,
