@@ -57,10 +57,11 @@ def release_cached_memory() -> None:
 class Operator:
     """A sparse operator ``M (+ diag)`` resident on the GPU (CSR of ``M`` and ``M^T``)."""
 
-    def __init__(self, handle, n, nnz):
+    def __init__(self, handle, n, nnz, diag=None):
         self._h = handle
         self.n = n
         self.nnz = nnz
+        self._diag = diag  # the current diagonal term: None or a float64 tensor (host or device)
 
     @classmethod
     def from_csr(cls, indptr, indices, data, diag=None, stream=None):
@@ -74,7 +75,7 @@ class Operator:
             raise ValueError("indices/data shorter than indptr[-1]")
         dptr = None
         if diag is not None:
-            diag = np.ascontiguousarray(diag, dtype=np.float64)
+            diag = np.array(diag, dtype=np.float64)  # a copy: kept as the operator's diagonal state
             if diag.shape != (n,):
                 raise ValueError("diag must have length n")
             dptr = diag.ctypes.data_as(ctypes.c_void_p)
@@ -83,7 +84,7 @@ class Operator:
                                          indices.ctypes.data_as(ctypes.c_void_p),
                                          data.ctypes.data_as(ctypes.c_void_p), dptr, _stream(stream),
                                          ctypes.byref(h)))
-        return cls(h, n, nnz)
+        return cls(h, n, nnz, None if diag is None else _torch().from_numpy(diag))
 
     @classmethod
     def from_scipy(cls, M, diag=None, stream=None):
@@ -92,10 +93,21 @@ class Operator:
         return cls.from_csr(M.indptr, M.indices, M.data, diag=diag, stream=stream)
 
     def set_diag(self, diag, stream=None):
-        """Replace the diagonal term by a device float64 vector (or remove it with None)."""
+        """Replace the diagonal term by a float64 vector (or remove it with None).
+
+        A host tensor is copied to the device first.  The operator remembers the vector
+        (``diag``), so that a caller can restore an earlier state."""
         lib = _lib.load()
+        if diag is not None and not diag.is_cuda:
+            diag = diag.to("cuda")
         ptr = None if diag is None else _dev_ptr(diag, "diag", (self.n,))
         _lib.check(lib.skr_op_set_diag(self._h, ptr, _stream(stream)))
+        self._diag = diag
+
+    @property
+    def diag(self):
+        """The current diagonal term (None or a float64 tensor)."""
+        return self._diag
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -271,29 +283,42 @@ def _make_pairing():
         Backward: one adjoint solve ``A^T Lam + Lam B^T = P1 P2^T`` with the same kernels,
         then ``dC1 = Lam C2``, ``dC2 = Lam^T C1``, ``dsigma = -diag(Lam X^T)``,
         ``dP1 = X P2``, ``dP2 = X^T P1`` (all scaled by the incoming gradient).
+        ``sigma = None`` solves with ``A0`` itself (no diagonal term).  Each of the two
+        solves sets its own ``sigma`` on ``A0`` and restores ``A0``'s previous diagonal
+        afterwards, so several forwards may run before their backwards.
         """
 
         @staticmethod
         def forward(ctx, C1, C2, sigma, P1, P2, A0, B, params):
             params = dict(params or {})
-            A0.set_diag(sigma.detach().contiguous() if sigma is not None else None)
-            res = solve(A0, B, C1.detach().contiguous(), C2.detach().contiguous(), **params)
+            sig = sigma.detach().clone().contiguous() if sigma is not None else None
+            prev = A0.diag
+            A0.set_diag(sig)
+            try:
+                res = solve(A0, B, C1.detach().contiguous(), C2.detach().contiguous(), **params)
+            finally:
+                A0.set_diag(prev)
             out = pairing_grads(res.X1, res.X2, C1.detach().contiguous(), C2.detach().contiguous(),
                                 P1.detach().contiguous(), P2.detach().contiguous(), want=())
             ctx.save_for_backward(C1, C2, P1, P2, res.X1, res.X2)
-            ctx.A0, ctx.B, ctx.params, ctx.has_sigma = A0, B, params, sigma is not None
+            ctx.A0, ctx.B, ctx.params, ctx.sigma = A0, B, params, sig
             ctx.fwd = res
             return torch.tensor(out["loss"], dtype=torch.float64, device=C1.device)
 
         @staticmethod
         def backward(ctx, g):
             C1, C2, P1, P2, X1, X2 = ctx.saved_tensors
-            adj = adjoint_solve(ctx.A0, ctx.B, P1.detach().contiguous(), P2.detach().contiguous(), **ctx.params)
+            prev = ctx.A0.diag
+            ctx.A0.set_diag(ctx.sigma)  # the operator of this forward, whatever ran since
+            try:
+                adj = adjoint_solve(ctx.A0, ctx.B, P1.detach().contiguous(), P2.detach().contiguous(), **ctx.params)
+            finally:
+                ctx.A0.set_diag(prev)
             ctx.adj = adj
             gr = pairing_grads(X1, X2, C1.detach().contiguous(), C2.detach().contiguous(), P1.detach().contiguous(),
                                P2.detach().contiguous(), L1=adj.X1, L2=adj.X2)
             gs = g.to(torch.float64)
-            dsig = gs * gr["dsig"] if ctx.has_sigma else None
+            dsig = gs * gr["dsig"] if ctx.sigma is not None else None
             return (gs * gr["dC1"], gs * gr["dC2"], dsig, gs * gr["dP1"], gs * gr["dP2"], None, None, None)
 
     return SylvesterPairing

@@ -84,3 +84,38 @@ def test_symmetric_adjoint_reproduces_forward():
     Xf = (f.X1 @ f.X2.T).cpu().numpy()
     Xa = (a.X1 @ a.X2.T).cpu().numpy()
     assert np.linalg.norm(Xf - Xa) <= 1e-12 * np.linalg.norm(Xf)
+
+
+def test_autograd_interleaved_forwards_use_their_own_sigma():
+    """Two forwards with different sigma on one operator before the first backward: the
+    backward must solve the adjoint of its own forward's operator, and the operator's
+    diagonal term is left as it was before the calls."""
+    import paper_2311_16019_amd as skr
+    torch = torch_cuda()
+    cfg, P1, P2 = _case(m=10)
+    prm = dict(k=2, maxit=50, p=2, s=416, tol=1e-10, seed=6)
+    base = np.full(cfg["n"], 0.25)
+    A0, B = gpu_ops(dict(cfg, sigma=base))  # created with a diagonal term of its own
+    sig1 = cfg["sigma"]
+    sig2 = 3.0 * cfg["sigma"] + 1.0
+
+    def leaf(x):
+        return to_dev(x).requires_grad_(True)
+
+    C1a, C2a, s1 = leaf(cfg["C1"]), leaf(cfg["C2"]), leaf(sig1)
+    La = skr.SylvesterPairing.apply(C1a, C2a, s1, to_dev(P1), to_dev(P2), A0, B, prm)
+    C1b, C2b, s2 = leaf(cfg["C1"]), leaf(cfg["C2"]), leaf(sig2)
+    Lb = skr.SylvesterPairing.apply(C1b, C2b, s2, to_dev(P1), to_dev(P2), A0, B, prm)
+    La.backward()
+    Lb.backward()
+    for sig, loss, t_c1, t_s in ((sig1, La, C1a, s1), (sig2, Lb, C1b, s2)):
+        dense = dense_grads(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], sig, P1, P2)
+        assert abs(loss.item() - dense["loss"]) <= 1e-8 * abs(dense["loss"])
+        for t, key in ((t_c1, "dC1"), (t_s, "dsigma")):
+            got = t.grad.cpu().numpy()
+            assert np.linalg.norm(got - dense[key]) <= 1e-6 * np.linalg.norm(dense[key]), key
+    # the operator's own diagonal is back: a plain solve sees A0 + diag(base)
+    assert np.array_equal(A0.diag.cpu().numpy(), base)
+    f = skr.solve(A0, B, to_dev(cfg["C1"]), to_dev(cfg["C2"]), **prm)
+    o = oracle_spksm(cfg["A"], cfg["B"], cfg["C1"], cfg["C2"], sigma=base, **prm)
+    assert product_distance(f, o) <= 1e-6

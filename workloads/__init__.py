@@ -14,6 +14,7 @@ from .stencil import (
     CSR,
     laplacian_2d,
     convdiff_2d_upwind,
+    convdiff_centered,
     diffusion_3d,
     vardiff_2d,
     lognormal_field_2d,
@@ -26,6 +27,7 @@ __all__ = [
     "CSR",
     "laplacian_2d",
     "convdiff_2d_upwind",
+    "convdiff_centered",
     "diffusion_3d",
     "vardiff_2d",
     "lognormal_field_2d",

@@ -12,6 +12,7 @@ import numpy as np
 from .factors import gaussian_block, gaussian_factors
 from .stencil import (
     convdiff_2d_upwind,
+    convdiff_centered,
     diffusion_3d,
     laplacian_2d,
     lognormal_field_2d,
@@ -35,7 +36,32 @@ CONFIGS = {
     # 2D log-normal variable-coefficient diffusion, A = B.
     "lognormal2d_2000": dict(dim=2, m=2000, r=10, k=2, maxit=200, s_per=2, tol=1e-6, p=20,
                              rhs_seed=15, sketch_seed=1005, field_seed=45, loss_seed=35),
+    # The paper's Example 6.1 (Sec. 6, Table 2): centered 2D convection-diffusion on 300^2
+    # nodes, w_A = (1, 1), w_B = (3y(1-x^2), -2x(1-y^2)), nu in {0.1, 0.01, 0.001},
+    # r in {1, 3}, k = 10, s = 1600, maxit = 800, tol 1e-6, p in {1, 20}.
+    "ex61_convdiff2d_300": dict(dim=2, m=300, r=1, k=10, maxit=800, s=1600, tol=1e-6, p=20, nu=0.1,
+                                rhs_seed=16, sketch_seed=1006),
+    # The paper's Example 6.3 (Sec. 6, Table 5): centered 3D convection-diffusion, nu = 0.005,
+    # w_A = (x sin x, y cos y, exp(z^2 - 1)), w_B = ((1 - x^2) y z, 1, exp(z)), n = m^3 with
+    # m in {50, 60, 70, 80, 90, 100}; r = 1, k = 3, s = 500, maxit = 250, tol 1e-6.
+    "ex63_convdiff3d_100": dict(dim=3, m=100, r=1, k=3, maxit=250, s=500, tol=1e-6, p=20, nu=0.005,
+                                rhs_seed=17, sketch_seed=1007),
 }
+
+
+def ex61_velocities():
+    """Convection fields of Example 6.1 (Sec. 6): ``w_A = (1, 1)``, ``w_B = (3y(1-x^2), -2x(1-y^2))``."""
+    wa = lambda x, y: (np.ones_like(x), np.ones_like(x))
+    wb = lambda x, y: (3.0 * y * (1.0 - x * x), -2.0 * x * (1.0 - y * y))
+    return wa, wb
+
+
+def ex63_velocities():
+    """Convection fields of Example 6.3 (Sec. 6): ``w_A = (x sin x, y cos y, e^{z^2-1})``,
+    ``w_B = ((1-x^2) y z, 1, e^z)``."""
+    wa = lambda x, y, z: (x * np.sin(x), y * np.cos(y), np.exp(z * z - 1.0))
+    wb = lambda x, y, z: ((1.0 - x * x) * y * z, np.ones_like(x), np.exp(z))
+    return wa, wb
 
 NU_CONVDIFF = 1e-2
 W_A = (1.0, 0.5)
@@ -44,7 +70,8 @@ ANISO = (1.0, 10.0, 100.0)
 CORR_LEN = 0.1
 
 
-def make_config(name: str, m: int | None = None, maxit: int | None = None, r: int | None = None) -> dict:
+def make_config(name: str, m: int | None = None, maxit: int | None = None, r: int | None = None,
+                nu: float | None = None) -> dict:
     """Build a workload: operators ``A``, ``B`` (CSR), factors and solver parameters.
 
     ``A`` may come with a separate nonnegative diagonal ``sigma`` (the reaction
@@ -58,6 +85,8 @@ def make_config(name: str, m: int | None = None, maxit: int | None = None, r: in
         c["maxit"] = maxit
     if r is not None:
         c["r"] = r
+    if nu is not None:
+        c["nu"] = nu
     mm = c["m"]
     sigma = None
     if name.startswith("laplace2d"):
@@ -74,6 +103,14 @@ def make_config(name: str, m: int | None = None, maxit: int | None = None, r: in
         B = A
         rng = np.random.Generator(np.random.PCG64(c["sigma_seed"]))
         sigma = rng.uniform(0.0, 1.0, size=A.n)
+    elif name.startswith("ex61"):
+        wa, wb = ex61_velocities()
+        A = convdiff_centered(mm, 2, c["nu"], wa)
+        B = convdiff_centered(mm, 2, c["nu"], wb)
+    elif name.startswith("ex63"):
+        wa, wb = ex63_velocities()
+        A = convdiff_centered(mm, 3, c["nu"], wa)
+        B = convdiff_centered(mm, 3, c["nu"], wb)
     elif name.startswith("lognormal2d"):
         kappa = lognormal_field_2d(mm, CORR_LEN, c["field_seed"])
         A = vardiff_2d(kappa)
@@ -84,8 +121,14 @@ def make_config(name: str, m: int | None = None, maxit: int | None = None, r: in
     C1, C2 = gaussian_factors(n, B.n, c["r"], c["rhs_seed"])
     out = dict(name=name, A=A, B=B, sigma=sigma, C1=C1, C2=C2, n=n, **{
         key: c[key] for key in ("m", "r", "k", "maxit", "tol", "p", "sketch_seed")})
-    s = c["s_per"] * c["maxit"] * c["r"]
+    if "s" in c:  # the paper's fixed sketch size (kept as s_paper for the DCT embedding)
+        out["s_paper"] = c["s"]
+        s = max(c["s"], (c["maxit"] + 1) * c["r"])
+    else:
+        s = c["s_per"] * c["maxit"] * c["r"]
     out["s"] = -(-s // 8) * 8  # a multiple of the sparse-sign column count
+    if "nu" in c:
+        out["nu"] = c["nu"]
     out["zeta"] = 8
     if "loss_seed" in c:
         out["P1"] = gaussian_block(n, 4, c["loss_seed"])

@@ -9,11 +9,15 @@ Conventions (shared by every operator built here):
   positive (``-Delta``-like) form, so its spectrum lies in the right half plane;
 * first-order upwind convection: for ``w_c > 0`` the backward neighbour in direction
   ``c`` carries ``-|w_c|/h`` (forward neighbour for ``w_c < 0``) and the diagonal
-  carries ``+|w_c|/h``.
+  carries ``+|w_c|/h``;
+* centered convection (``convdiff_centered``, the scheme of the paper's Sec. 6): the
+  forward neighbour in direction ``c`` carries ``+w_c(x)/(2h)`` and the backward one
+  ``-w_c(x)/(2h)``, with the velocity evaluated at the node.
 
 The operators mirror the convection-diffusion workloads of the paper's experiments
-(Sec. 6, Example 6.1 on the unit square and Example 6.3 on the unit cube); the
-upwind scheme and the variable-coefficient diffusion are this package's choices.
+(Sec. 6, Example 6.1 on the unit square and Example 6.3 on the unit cube):
+``convdiff_centered`` builds those examples' operators; the upwind scheme and the
+variable-coefficient diffusion of the other workloads are this package's choices.
 """
 from __future__ import annotations
 
@@ -160,6 +164,41 @@ def lognormal_field_2d(m: int, corr_len: float, seed: int, pad: int = 2) -> np.n
     g = np.fft.irfft2(np.fft.rfft2(xi) * amp, s=(N, N))[:m, :m]
     g = (g - g.mean()) / g.std()
     return np.exp(g)
+
+
+def convdiff_centered(m: int, dim: int, nu: float, wfun) -> CSR:
+    """``-nu Delta u + w(x) . grad u`` by centered differences on an ``m^dim`` grid.
+
+    ``wfun(*coords)`` returns the ``dim`` velocity components at the given node
+    coordinates (arrays of the grid's shape, ``coords[0]`` = x).  Per direction ``c``
+    the node's row gets ``2 nu / h^2`` on the diagonal and
+    ``-nu / h^2 +- w_c / (2h)`` on the forward (+) and backward (-) neighbours; a
+    neighbour outside the domain is a homogeneous Dirichlet value and drops out.
+    """
+    h = 1.0 / (m + 1)
+    x = (np.arange(m) + 1) * h
+    shape = (m,) * dim
+    # grid arrays indexed [.., iz, iy, ix] so that ravel() is the x-fastest ordering
+    grids = np.meshgrid(*([x] * dim), indexing="ij")[::-1]  # grids[c] varies along axis dim-1-c
+    w = [np.broadcast_to(np.asarray(wc, dtype=np.float64), shape) for wc in wfun(*grids)]
+    if len(w) != dim:
+        raise ValueError("wfun must return one velocity component per direction")
+    idx = np.arange(m**dim).reshape(shape)
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [np.full(m**dim, 2.0 * dim * nu / h**2)]
+    for c in range(dim):
+        ax = dim - 1 - c  # the array axis of direction c
+        lo = [slice(None)] * dim
+        hi = [slice(None)] * dim
+        lo[ax] = slice(0, m - 1)
+        hi[ax] = slice(1, m)
+        lo, hi = tuple(lo), tuple(hi)
+        # forward neighbour of the nodes in `lo` is the node in `hi`, and vice versa
+        rows += [idx[lo].ravel(), idx[hi].ravel()]
+        cols += [idx[hi].ravel(), idx[lo].ravel()]
+        vals += [-nu / h**2 + w[c][lo].ravel() / (2 * h), -nu / h**2 - w[c][hi].ravel() / (2 * h)]
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m**dim, m**dim))
+    return CSR.from_scipy(M.tocsr())
 
 
 def with_diag_shift(A: CSR, sigma: np.ndarray) -> CSR:
