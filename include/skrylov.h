@@ -237,6 +237,30 @@ SKR_API int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q,
                       double* loss, double* dC1, double* dC2, double* dsig,
                       double* dP1, double* dP2, void* stream);
 
+/*
+ * skr_pairing_grads for callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and loss, but every temporary lives in one fixed device workspace of
+ * SKR_PAIRING_SCRATCH_BYTES per device, which the library's code object holds from its load
+ * until the process ends.  The call makes no hipMalloc/hipFree and no allocating library
+ * call; the caller still provides every input and output buffer.  The temporaries are
+ * 2 q ellx + (q ellx for each of dP1, dP2) + (elll r for each of dC1, dC2) + elll ellx (dsig)
+ * doubles plus the partial sums of the long reductions (at most 256 of the largest of those
+ * products); dsig needs room for at least one more row of ellx doubles and works through
+ * the rows in chunks that fit.  Sizes beyond the workspace return SKR_EINVAL before any work
+ * is queued.  The workspace is shared by every call on a device and keeps the last call's
+ * contents (nothing in it needs to start at zero): the call synchronises `stream` before it
+ * returns, so calls made one after another never overlap, but calls that overlap on one
+ * device (from several host threads) race on the workspace and must not be made.
+ */
+#define SKR_PAIRING_SCRATCH_BYTES (32ll << 20)
+SKR_API int skr_pairing_grads_noalloc(int64_t n1, int64_t n2, int64_t r, int64_t q,
+                      const double* X1, const double* X2, int64_t ellx,
+                      const double* L1, const double* L2, int64_t elll,
+                      const double* C1, const double* C2, const double* P1, const double* P2,
+                      double* loss, double* dC1, double* dC2, double* dsig,
+                      double* dP1, double* dP2, void* stream);
+
 /* Device memory and streams released by finished calls are kept by the library and
  * reused by later calls (a solve allocates its stored bases, gigabytes at large n, and
  * several streams).  This returns every cached block of every device to the HIP runtime;

@@ -64,6 +64,8 @@ SIGNATURES = {
     "skr_true_residual": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),
     "skr_pairing_grads": (_i32, [_i64, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                                  _pf64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "skr_pairing_grads_noalloc": (_i32, [_i64, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp,
+                                         _vp, _pf64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "skr_lyap_solve": (_i32, [_vp, _vp, _i64, ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
     "skr_release_cached_memory": (_i32, []),
     "skr_last_error": (ctypes.c_char_p, []),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "dense.hpp"
@@ -481,6 +482,140 @@ extern "C" int skr_pairing_grads(int64_t n1, int64_t n2, int64_t r, int64_t q, c
     }
     double h = 0.0;
     SKR_HIP(hipMemcpyAsync(&h, out.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    SKR_HIP(hipStreamSynchronize(st));
+    if (loss) *loss = h;
+    return SKR_OK;
+  });
+}
+
+// ------------------------------------------------------------ allocation-free gradients
+// skr_pairing_grads_noalloc keeps every temporary in `scratch`, a fixed device array of
+// SKR_PAIRING_SCRATCH_BYTES that each device holds from the module load until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current and kept in g_scratch_dev.
+namespace {
+
+constexpr size_t SCRATCH_DOUBLES = SKR_PAIRING_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+double* scratch_on_current_device() {
+  int dev = 0;
+  SKR_HIP(hipGetDevice(&dev));
+  SKR_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw Error(SKR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+
+// Offsets of consecutive 256-byte aligned pieces of the scratch array (in doubles).
+struct Carver {
+  size_t used = 0;
+  size_t take(size_t count) {
+    const size_t start = (used + 31) / 32 * 32;
+    used = start + count;
+    return start;
+  }
+};
+
+}  // namespace
+
+extern "C" int skr_pairing_grads_noalloc(int64_t n1, int64_t n2, int64_t r, int64_t q, const double* X1,
+                                         const double* X2, int64_t ellx, const double* L1, const double* L2,
+                                         int64_t elll, const double* C1, const double* C2, const double* P1,
+                                         const double* P2, double* loss, double* dC1, double* dC2, double* dsig,
+                                         double* dP1, double* dP2, void* stream) {
+  return guarded([&] {
+    SKR_REQUIRE(n1 > 0 && n2 > 0 && r > 0 && q > 0 && ellx > 0, "sizes must be positive");
+    SKR_REQUIRE(n1 <= INT_MAX && n2 <= INT_MAX && r <= INT_MAX && q <= INT_MAX && ellx <= INT_MAX && elll <= INT_MAX,
+                "sizes must fit in 32 bits");
+    SKR_REQUIRE(X1 && X2 && P1 && P2, "null argument");
+    const bool adj = dC1 || dC2 || dsig;
+    SKR_REQUIRE(!adj || (L1 && L2 && elll > 0), "adjoint factors required for dC1, dC2, dsig");
+    SKR_REQUIRE(!dC1 || C2, "C2 required for dC1");
+    SKR_REQUIRE(!dC2 || C1, "C1 required for dC2");
+    hipStream_t st = as_stream(stream);
+    const int N1 = (int)n1, N2 = (int)n2, R = (int)r, Q = (int)q, LX = (int)ellx, LL = (int)elll;
+    // Lay out the temporaries as offsets and reject an oversized request before any work
+    // is queued.  Z (the rows of L1 (L2^T X2) that the dsig kernel reads) takes what is left,
+    // at least one row.
+    Carver c;
+    const size_t o_a = c.take((size_t)Q * LX), o_b = c.take((size_t)Q * LX), o_out = c.take(1);
+    const size_t o_sp1 = dP1 ? c.take((size_t)LX * Q) : 0, o_sp2 = dP2 ? c.take((size_t)LX * Q) : 0;
+    const size_t o_sc1 = dC1 ? c.take((size_t)LL * R) : 0, o_sc2 = dC2 ? c.take((size_t)LL * R) : 0;
+    const size_t o_ss = dsig ? c.take((size_t)LL * LX) : 0;
+    size_t ws_n = 0;  // split-K partials of the longest reduction, reused call after call
+    ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, Q, LX, N1));
+    ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, Q, LX, N2));
+    if (dP1) ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, LX, Q, N2));
+    if (dP2) ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, LX, Q, N1));
+    if (dC1) ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, LL, R, N2));
+    if (dC2) ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, LL, R, N1));
+    if (dsig) ws_n = std::max(ws_n, dense::gemm_workspace_doubles(false, true, LL, LX, N2));
+    const size_t o_ws = c.take(ws_n);
+    int zrows = 0;
+    size_t o_z = 0;
+    if (dsig) {
+      o_z = c.take(0);
+      const size_t left = o_z < SCRATCH_DOUBLES ? SCRATCH_DOUBLES - o_z : 0;
+      zrows = (int)std::min<size_t>(left / (size_t)LX, (size_t)N1);
+      c.used = o_z + (size_t)zrows * LX;
+    }
+    if (c.used > SCRATCH_DOUBLES || (dsig && zrows < 1))
+      throw Error(SKR_EINVAL, "skr_pairing_grads_noalloc: the temporaries of these sizes exceed the " +
+                                  std::to_string((long long)SKR_PAIRING_SCRATCH_BYTES) + "-byte device workspace");
+    double* base = scratch_on_current_device();
+    double *a = base + o_a, *b = base + o_b, *out = base + o_out, *sp1 = base + o_sp1, *sp2 = base + o_sp2;
+    double *sc1 = base + o_sc1, *sc2 = base + o_sc2, *ss = base + o_ss, *ws = ws_n ? base + o_ws : nullptr;
+    double* Z = base + o_z;
+    auto inner_ws = [&](int n, int c1, int c2, const double* M1, const double* M2, double* S) {
+      dense::gemm_ws(false, true, c1, c2, n, 1.0, M1, c1, M2, c2, 0.0, S, c1, ws, ws_n, st);
+    };
+    auto outer_ws = [&](int n, int c1, int c2, const double* M, const double* S, double* O) {
+      dense::gemm_ws(true, false, c2, n, c1, 1.0, S, c1, M, c1, 0.0, O, c2, nullptr, 0, st);
+    };
+    inner_ws(N1, Q, LX, P1, X1, a);
+    inner_ws(N2, Q, LX, P2, X2, b);
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(256), 0, st, Q * LX, a, b, out);
+    check_launch("dot");
+    if (dP1) {  // X1 (X2^T P2)
+      inner_ws(N2, LX, Q, X2, P2, sp1);
+      outer_ws(N1, LX, Q, X1, sp1, dP1);
+    }
+    if (dP2) {  // X2 (X1^T P1)
+      inner_ws(N1, LX, Q, X1, P1, sp2);
+      outer_ws(N2, LX, Q, X2, sp2, dP2);
+    }
+    if (dC1) {  // L1 (L2^T C2)
+      inner_ws(N2, LL, R, L2, C2, sc1);
+      outer_ws(N1, LL, R, L1, sc1, dC1);
+    }
+    if (dC2) {  // L2 (L1^T C1)
+      inner_ws(N1, LL, R, L1, C1, sc2);
+      outer_ws(N2, LL, R, L2, sc2, dC2);
+    }
+    if (dsig) {  // -rowsum((L1 (L2^T X2)) o X1), zrows rows at a time
+      inner_ws(N2, LL, LX, L2, X2, ss);
+      for (int i0 = 0; i0 < N1; i0 += zrows) {
+        const int rows = std::min(zrows, N1 - i0);
+        outer_ws(rows, LL, LX, L1 + (size_t)i0 * LL, ss, Z);
+        hipLaunchKernelGGL(rowdot_kernel, dim3(std::min(8192, ceil_div(rows, 16))), dim3(256), 0, st, rows, LX, Z,
+                           X1 + (size_t)i0 * LX, dsig + i0);
+        check_launch("rowdot");
+      }
+    }
+    double h = 0.0;
+    SKR_HIP(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, st));
     SKR_HIP(hipStreamSynchronize(st));
     if (loss) *loss = h;
     return SKR_OK;

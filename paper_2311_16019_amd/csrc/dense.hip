@@ -176,21 +176,35 @@ void run_gemm(int m, int n, int k, LA la, LB lb, ST st, hipStream_t s) {
 
 // Few output tiles and a long reduction: split K over workgroups into partial products
 // and sum them in a fixed order (column-major C only).
-template <class LA, class LB>
-bool run_gemm_splitk(int m, int n, int k, LA la, LB lb, double alpha, double beta, double* C, int ldc, hipStream_t s) {
+// Number of K slices and their length for a split-K product, or false when the product
+// is not split (many output tiles or a short reduction).
+bool splitk_plan(int m, int n, int k, int* nz_out, int* kchunk_out) {
   const int tiles = ceil_div(m, BM) * ceil_div(n, BN);
   if (tiles >= 64 || k < 8192) return false;
   int nz = std::min(512 / tiles + 1, ceil_div(k, 2048));
   nz = std::max(2, std::min(nz, 256));
   const int kchunk = ceil_div(ceil_div(k, nz), BK) * BK;
-  nz = ceil_div(k, kchunk);
-  DBuf<double> W((size_t)nz * m * n);
-  StoreCM sw{W.p, m, 1.0, 0.0, (size_t)m * n};
+  *nz_out = ceil_div(k, kchunk);
+  *kchunk_out = kchunk;
+  return true;
+}
+
+// ws: caller-provided room for the nz m x n partial products, or null to take it from the
+// device-memory cache.
+template <class LA, class LB>
+bool run_gemm_splitk(int m, int n, int k, LA la, LB lb, double alpha, double beta, double* C, int ldc, double* ws,
+                     hipStream_t s) {
+  int nz = 0, kchunk = 0;
+  if (!splitk_plan(m, n, k, &nz, &kchunk)) return false;
+  DBuf<double> W;
+  if (!ws) W.alloc((size_t)nz * m * n);
+  double* wp = ws ? ws : W.p;
+  StoreCM sw{wp, m, 1.0, 0.0, (size_t)m * n};
   dim3 grid(ceil_div(m, BM), ceil_div(n, BN), nz);
   hipLaunchKernelGGL((gemm_kernel<LA, LB, StoreCM>), grid, dim3(GT), 0, s, m, n, k, la, lb, sw, kchunk);
   check_launch("gemm_splitk");
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(std::min(2048, ceil_div((int64_t)m * n, 256))), dim3(256), 0, s, m, n,
-                     nz, W.p, alpha, beta, C, ldc);
+                     nz, wp, alpha, beta, C, ldc);
   check_launch("splitk_reduce");
   return true;  // W returns to the device-memory cache, which orders its reuse after this work
 }
@@ -368,6 +382,29 @@ int red_grid(size_t total) { return (int)std::max<size_t>(1, std::min<size_t>(RE
 
 int scratch_doubles() { return 3 * RED_MAXG; }
 
+size_t gemm_workspace_doubles(bool ta, bool tb, int m, int n, int k) {
+  int nz = 0, kchunk = 0;
+  if (k <= 0 || ta == tb || !splitk_plan(m, n, k, &nz, &kchunk)) return 0;
+  return (size_t)nz * m * n;
+}
+
+void gemm_ws(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+             double beta, double* C, int ldc, double* ws, size_t ws_doubles, hipStream_t st) {
+  if (gemm_workspace_doubles(ta, tb, m, n, k) > ws_doubles) throw Error(SKR_EINVAL, "gemm workspace too small");
+  StoreCM sc{C, ldc, alpha, beta};
+  if (k <= 0) {  // C = beta C
+    if (beta == 0.0) set_zero(m, n, C, ldc, st);
+    else if (beta != 1.0) throw Error(SKR_ENOTSUP, "gemm with k = 0 and beta != 0, 1");
+    return;
+  }
+  if (ta && !tb && run_gemm_splitk(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, alpha, beta, C, ldc, ws, st)) return;
+  if (!ta && tb && run_gemm_splitk(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, alpha, beta, C, ldc, ws, st)) return;
+  if (!ta && !tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBN{B, ldb}, sc, st);
+  else if (ta && !tb) run_gemm(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, sc, st);
+  else if (!ta && tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, sc, st);
+  else run_gemm(m, n, k, LoadAT{A, lda}, LoadBT{B, ldb}, sc, st);
+}
+
 void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc, hipStream_t st) {
   StoreCM sc{C, ldc, alpha, beta};
@@ -376,8 +413,8 @@ void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, 
     else if (beta != 1.0) throw Error(SKR_ENOTSUP, "gemm with k = 0 and beta != 0, 1");
     return;
   }
-  if (ta && !tb && run_gemm_splitk(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, alpha, beta, C, ldc, st)) return;
-  if (!ta && tb && run_gemm_splitk(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, alpha, beta, C, ldc, st)) return;
+  if (ta && !tb && run_gemm_splitk(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, alpha, beta, C, ldc, nullptr, st)) return;
+  if (!ta && tb && run_gemm_splitk(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, alpha, beta, C, ldc, nullptr, st)) return;
   if (!ta && !tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBN{B, ldb}, sc, st);
   else if (ta && !tb) run_gemm(m, n, k, LoadAT{A, lda}, LoadBN{B, ldb}, sc, st);
   else if (!ta && tb) run_gemm(m, n, k, LoadAN{A, lda}, LoadBT{B, ldb}, sc, st);

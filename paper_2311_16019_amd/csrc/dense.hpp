@@ -11,6 +11,13 @@ namespace dense {
 // C = alpha * op(A) op(B) + beta * C,  op(X) = X or X^T
 void gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc, hipStream_t st);
+// The same product with the split-K partial products (long reductions with few output
+// tiles) in a caller-provided workspace of ws_doubles doubles instead of the device-memory
+// cache; gemm_workspace_doubles gives the size it needs (0 when the product is not split).
+// Allocates nothing; SKR_EINVAL when the workspace is too small.
+void gemm_ws(bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+             double beta, double* C, int ldc, double* ws, size_t ws_doubles, hipStream_t st);
+size_t gemm_workspace_doubles(bool ta, bool tb, int m, int n, int k);
 
 // X1 (n x l, row-major, ld ldx) = alpha * sum_j U_j W[j r : (j+1) r, :] + beta * X1, where the
 // basis blocks U_j (n x r, row-major) are stored consecutively (block j at U + j n r) and W is
