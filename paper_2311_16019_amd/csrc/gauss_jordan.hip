@@ -34,6 +34,11 @@ constexpr int GJ_MAXUPD = 511;    // update workgroups per launch
 
 struct GjArgs {
   int n, ncols, ld, b, nblk, nupd;
+  // column range of this elimination: columns c0 .. c0 + npiv - 1 are eliminated, and the
+  // update workgroups touch only columns c0 .. cend - 1 (the whole matrix for a one-level
+  // elimination; one outer panel of a two-level elimination)
+  int c0, npiv, cend;
+  int want_logdet;    // the final launch sums log|pivot| over all n columns
   int wide;           // columns are 16-byte aligned (even ld, aligned S)
   double* S;
   int* piv;
@@ -123,7 +128,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   __shared__ double red[GJ_W];
   const int tid = threadIdx.x, wv = tid / 64;
   if (g.b == g.nblk) {  // final launch: log|det A| = sum of log|pivot|, in a fixed order
-    if (g.logabsdet) {
+    if (g.logabsdet && g.want_logdet) {
       double l = 0.0;
       for (int k = tid; k < g.n; k += GJ_T) l += (g.pivabs[k] > 0.0) ? log(g.pivabs[k]) : 0.0;
       l = wave_sum(l);
@@ -137,7 +142,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     }
     return;
   }
-  const int k0 = g.b * NB, nbc = min(NB, g.n - k0);
+  const int k0 = g.c0 + g.b * NB, nbc = min(NB, g.c0 + g.npiv - k0);
   constexpr int ROWS = GJ_T * RPT;
   const int kp0 = k0 - NB;
   if (g.b > 0) {
@@ -303,8 +308,8 @@ __device__ void update_workgroup(const GjArgs& g) {
   __shared__ int pl[NB];
   __shared__ double am[NB][GJ_CW];
   const int tid = threadIdx.x;
-  const int kp0 = (g.b - 1) * NB, nbp = min(NB, g.n - kp0);
-  const int kb0 = g.b * NB, kb1 = (g.b < g.nblk) ? min(g.n, kb0 + NB) : kb0;
+  const int kp0 = g.c0 + (g.b - 1) * NB, nbp = min(NB, g.c0 + g.npiv - kp0);
+  const int kb0 = g.c0 + g.b * NB, kb1 = (g.b < g.nblk) ? min(g.c0 + g.npiv, kb0 + NB) : kb0;
   if (tid < nbp) pl[tid] = g.piv[kp0 + tid];
   __syncthreads();
   double s[RPT][NB];
@@ -319,10 +324,10 @@ __device__ void update_workgroup(const GjArgs& g) {
     for (int t = 0; t < nbp; ++t)
       if (pl[t] == row) tp[q] = t;
   }
-  auto skip = [&](int j) { return j >= g.ncols || (j >= kp0 && j < kp0 + nbp) || (j >= kb0 && j < kb1); };
-  const int nstrips = (g.ncols + GJ_CW - 1) / GJ_CW;
+  auto skip = [&](int j) { return j >= g.cend || (j >= kp0 && j < kp0 + nbp) || (j >= kb0 && j < kb1); };
+  const int nstrips = (g.cend - g.c0 + GJ_CW - 1) / GJ_CW;
   for (int strip = blockIdx.x - 1; strip < nstrips; strip += g.nupd) {
-    const int j0 = strip * GJ_CW;
+    const int j0 = g.c0 + strip * GJ_CW;
     for (int e = tid; e < NB * GJ_CW; e += GJ_T) {
       const int t = e / GJ_CW, jj = e % GJ_CW, j = j0 + jj;
       am[t][jj] = (t < nbp && !skip(j)) ? g.S[pl[t] + (size_t)j * g.ld] : 0.0;
@@ -404,6 +409,52 @@ __global__ void gj_apply_gather_kernel(int n, int nch, const int* piv, const dou
   y[i] = t;
 }
 
+// Outer panel update of a two-level elimination: after the columns K_B = c0 .. c0 + w - 1
+// have been eliminated (their columns hold E_B(:, P_B)), every other column j receives
+//     S(:, j) <- S(:, j) + S(:, K_B) a_j - sum_t a_j(t) e_{P_B[t]},   a_j = S(P_B, j),
+// as one gather of the pivot rows, two GEMMs on the matrix cores and one scatter.
+__global__ void gj_gather_rows_kernel(int w, int c0, int ncols, const double* S, int ld, const int* piv, double* A) {
+  const size_t total = (size_t)w * ncols;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e % w), j = (int)(e / w);
+    const bool inside = j >= c0 && j < c0 + w;
+    A[e] = inside ? 0.0 : S[piv[c0 + t] + (size_t)j * ld];
+  }
+}
+
+__global__ void gj_scatter_rows_kernel(int w, int c0, int ncols, double* S, int ld, const int* piv, const double* A) {
+  const size_t total = (size_t)w * ncols;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e % w), j = (int)(e / w);
+    if (j >= c0 && j < c0 + w) continue;
+    S[piv[c0 + t] + (size_t)j * ld] -= A[e];
+  }
+}
+
+// One elimination range (all columns for a one-level elimination, one outer panel of a
+// two-level one): launches b = 0 .. nblk of gj_step_kernel.
+template <int RPT, int NB>
+void run_gj_range(GjArgs g, hipStream_t st) {
+  g.nblk = (g.npiv + NB - 1) / NB;
+  g.nupd = std::min(GJ_MAXUPD, (g.cend - g.c0 + GJ_CW - 1) / GJ_CW);
+  const int lds_bytes = GJ_T * RPT * NB * (int)sizeof(double);
+  SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds_bytes));
+  for (int b = 0; b <= g.nblk; ++b) {
+    g.b = b;
+    const int grid = (b == 0) ? 1 : 1 + g.nupd;
+    // only launches with a previous panel stage it; the update workgroups need no LDS
+    hipLaunchKernelGGL((gj_step_kernel<RPT, NB>), dim3(grid), dim3(GJ_T), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
+    check_launch("gj_step");
+  }
+}
+
+// Columns per outer panel of the two-level elimination, used from GJ2_MIN_N rows on: the
+// one-level panels there are a few columns wide (all n rows of a panel are held in one
+// workgroup's registers) and every panel is a rank-NB update of the whole matrix, a pass
+// over n x ncols doubles per few columns; the outer panels turn that traffic into GEMMs.
+constexpr int GJ2_W = 256, GJ2_MIN_N = 1025;
+
 template <int RPT, int NB>
 void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
             hipStream_t st) {
@@ -412,8 +463,6 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
   g.ncols = ncols;
   g.ld = lds;
   g.wide = (lds % 2 == 0) && (reinterpret_cast<uintptr_t>(S) % 16 == 0);
-  g.nblk = (n + NB - 1) / NB;
-  g.nupd = std::min(GJ_MAXUPD, (ncols + GJ_CW - 1) / GJ_CW);
   g.S = S;
   g.piv = iws;
   g.pos = iws + n;
@@ -424,15 +473,35 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
   hipLaunchKernelGGL(gj_init_kernel, dim3(std::max(1, std::min(64, ceil_div(n, 256)))), dim3(256), 0, st, n, g.used,
                      info);
   check_launch("gj_init");
-  const int lds_bytes = GJ_T * RPT * NB * (int)sizeof(double);
-  SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lds_bytes));
-  for (int b = 0; b <= g.nblk; ++b) {
-    g.b = b;
-    const int grid = (b == 0) ? 1 : 1 + g.nupd;
-    // only launches with a previous panel stage it; the update workgroups need no LDS
-    hipLaunchKernelGGL((gj_step_kernel<RPT, NB>), dim3(grid), dim3(GJ_T), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
-    check_launch("gj_step");
+  if (n < GJ2_MIN_N) {
+    g.c0 = 0;
+    g.npiv = n;
+    g.cend = ncols;
+    g.want_logdet = 1;
+    run_gj_range<RPT, NB>(g, st);
+    return;
+  }
+  static_assert(GJ2_W % NB == 0, "outer panels hold whole inner panels");
+  const int wmax = std::min(GJ2_W, n);
+  DBuf<double> A((size_t)wmax * ncols);  // pivot rows of the other columns; reused panel after panel
+  for (int c0 = 0; c0 < n; c0 += GJ2_W) {
+    const int w = std::min(GJ2_W, n - c0);
+    g.c0 = c0;
+    g.npiv = w;
+    g.cend = c0 + w;
+    g.want_logdet = (c0 + w == n);
+    run_gj_range<RPT, NB>(g, st);
+    if (ncols == w) continue;
+    const int grid = std::max(1, std::min(4096, ceil_div((int64_t)w * ncols, 256)));
+    hipLaunchKernelGGL(gj_gather_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, g.piv, A.p);
+    check_launch("gj_gather_rows");
+    const double* K = S + (size_t)c0 * lds;
+    if (c0 > 0) gemm(false, false, n, c0, w, 1.0, K, lds, A.p, w, 1.0, S, lds, st);
+    if (c0 + w < ncols)
+      gemm(false, false, n, ncols - c0 - w, w, 1.0, K, lds, A.p + (size_t)(c0 + w) * w, w, 1.0,
+           S + (size_t)(c0 + w) * lds, lds, st);
+    hipLaunchKernelGGL(gj_scatter_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, g.piv, A.p);
+    check_launch("gj_scatter_rows");
   }
 }
 

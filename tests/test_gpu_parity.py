@@ -187,3 +187,19 @@ def test_indefinite_operators_take_the_deflated_solve(precision):
     tol_x, tol_h = TOL[precision]
     assert product_distance(g, o) <= tol_x
     assert history_ratio(g, o) <= tol_h
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_projected_size(precision):
+    """r = 16 and d = 70 on the 64 x 64 Laplacian pair: projected matrices of order 1120,
+    where the Gauss-Jordan inversions of the sign iteration run in outer panels whose
+    updates of the other columns are GEMMs (one-level elimination below order 1025)."""
+    cfg = make_config("laplace2d_64", r=16)
+    prm = dict(k=2, maxit=70, p=35, s=2240, seed=1001, tol=0.0)
+    print(f"large projected size laplace 64 r=16 d=70 {precision}", flush=True)
+    g, _ = gpu_solve(cfg, precision=precision, **prm)
+    o = oracle_solve(cfg, **prm)
+    assert g.iters == o.d == 70
+    tol_x, tol_h = TOL[precision]
+    assert product_distance(g, o) <= tol_x
+    assert history_ratio(g, o) <= tol_h
