@@ -1,17 +1,28 @@
-"""Benchmark: Krylov block steps/s of the s-PKSM hot path at n = 1e6 on one MI355X.
+"""Benchmark: time to a true relative residual of 1e-6, and Krylov block steps/s, of the
+s-PKSM forward + adjoint solve at n = 1e6 on one MI355X, in FP64 and in mixed precision.
 
-One benchmark step = a forward solve of A X + X B = C1 C2^T and the adjoint solve
-A^T L + L B^T = P1 P2^T with the same method, then the gradients of tr(P1^T X P2), on the
-1000 x 1000 upwind convection-diffusion pair (n = 1e6, r = 4, k = 3, s = 8000,
-nu = 1e-2, w_A = (1, 0.5), w_B = (-0.3, 1)).  Each solve runs a fixed window of d block
-steps (tandem SpMM, truncated block Gram-Schmidt, sketch, sketched QR update), one
-projected FP64 Sylvester solve with the residual estimate, the low-rank factorisation and
-the stored-basis recovery.  `value` = tandem block steps (forward + adjoint) per second
-of wall time over the whole step, inputs resident in HBM.
+Workload: the 1000 x 1000 upwind convection-diffusion pair (n = 1e6, nu = 1e-2,
+w_A = (1, 0.5), w_B = (-0.3, 1)), r = 4 Gaussian right-hand-side factors, loss
+tr(P1^T X P2) with P1, P2 n x 4 Gaussian.  One benchmark step = the forward solve of
+A X + X B = C1 C2^T run to the relative residual estimate 1e-6 (Algorithm 1, checked every
+p block steps), the adjoint solve A^T L + L B^T = P1 P2^T run the same way, and the
+gradients dC1, dC2, dP1, dP2 -- every phase on the GPU, inputs resident in HBM.  After the
+timed steps the true relative residuals of both solves are evaluated (the pass condition of
+the time-to-solution figure).
 
-Also reported: the same step in plain FP64, the per-kernel roofline of the dominant
-kernel family (HIP events inside the timed region), and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+Truncation: the pair's nonsymmetric operators make the k = 3 truncated bases numerically
+dependent before 1e-6 is reached (the sketched basis factor T becomes singular and the
+projected matrices acquire spurious eigenvalues in the left half plane, near d = 600 at this
+size); k = 10, the paper's choice for its convection-diffusion example (Sec. 6, Ex. 6.1),
+keeps T well conditioned and converges near d = 1300.  The sketch size follows the
+workload's formula s = 4 maxit r with maxit = 1.25 x the FP64 stopping step.
+
+`value` = tandem block steps (forward + adjoint) per second of wall time over the whole
+FP64 step; `ms_per_step` is the FP64 forward + adjoint time to solution.  The line also
+carries the mixed-precision step (FP32 bulk, FP64 small work) at the same tolerance, the
+block-step throughput over a fixed window with the workload's own k = 3, the roofline of
+the dominant block-step kernel, and the FP64 CPU oracle's time on the host cores (bounded
+measured samples, extrapolated to the same solve).
 """
 import argparse
 import json
@@ -26,26 +37,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "convdiff2d_1000"
+# time-to-solution solve: k, check period, maxit (1.25 x the FP64 stopping step, 1500)
+TTS = dict(k=10, p=250, maxit=1875, tol=1e-6)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--window", type=int, default=200, help="block steps per solve")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--window", type=int, default=200, help="block steps of the fixed-window k = 3 legs")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision time-to-solution step")
+    ap.add_argument("--no-window", action="store_true", help="skip the fixed-window k = 3 throughput legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-tpksm", action="store_true", help="skip the t-PKSM comparison solve")
     ap.add_argument("--no-lyapunov", action="store_true", help="skip the Lyapunov comparison solve")
     ap.add_argument("--no-sorth", action="store_true",
                     help="skip the solve with the sketched-inner-product orthogonalisation")
     ap.add_argument("--no-srht", action="store_true", help="skip the solve with the subsampled randomized DCT")
-    ap.add_argument("--concurrent", action="store_true",
-                    help="run the forward and the adjoint solve of a step concurrently (two host threads, "
-                         "one stream each)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB: run only a plain device-to-device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -53,14 +62,13 @@ def parse():
 
 # Kernel sources whose change invalidates a stored counter measurement of the SpMM kernel.
 SPMM_SOURCES = ["block_cgs.hip", "blockstep.hpp", "small_la.hpp"]
-TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                              "traffic_spmm_convdiff1000_r4_mixed.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_spmm_convdiff1000_r4_mixed.md")
 
 
 def spmm_sources_digest():
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_16019_amd", "csrc")
+    csrc = os.path.join(ROOT, "paper_2311_16019_amd", "csrc")
     for name in SPMM_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
@@ -109,58 +117,118 @@ def sell_bytes(M, w):
     return entries * (w + 4) + 4 * (ns + 1)
 
 
-def algorithmic_bytes(family, cfg, w, d_avg):
+def csr_bytes(M, w):
+    """Bytes of one sweep over M in CSR form: values, int32 columns and row pointers."""
+    return M.nnz * (w + 4) + 4 * (M.shape[0] + 1)
+
+
+def algorithmic_bytes(family, cfg, w, k, d_avg, s, two_pass):
     """Bytes one launch of a kernel family must move (both Krylov spaces), by its definition.
 
-    w = bulk element size, blocks are n x r; k window blocks.  spmm: the operator in its
-    sliced-ELL form streamed once (padded entries (w + 4) + 4 (slices + 1), the mean of the
-    forward orientations A, B^T and the adjoint ones A^T, B), U_d read once, U~ written,
-    the diagonal shift of A read.  dots: U~ and the k window blocks
-    read.  update: U~ and the window read, U_{d+1} written.  sketch: U_{d+1} and the
-    2-byte embedding table (zeta entries per row) read, s x r FP64 written.  whiten: the
-    FP64 sketched basis Q (s x d r) read once.
+    w = bulk element size, blocks are n x r, k window blocks.  Two-pass block step (r <= 4,
+    k <= 3; sliced-ELL SpMM): spmm = the operator streamed once (the mean of the forward
+    orientations A, B^T and the adjoint ones A^T, B), U_d read, U~ written; dots = U~ and the
+    window read; update = U~ and the window read, U_{d+1} written.  Block MGS step (CSR
+    SpMM): spmm = the operator, U_d and the first window block read, U~ written; dots = one
+    Gram-Schmidt update (U~ and one window block read, U~ written, the next window block
+    read for its product; the last update of a step reads no next block); update = the
+    second Cholesky QR pass and the normalisation (U~ read three times, U_{d+1} written).
+    whiten: the FP64 sketched basis Q (s x d r) read once.
     """
-    n, r, s, k = cfg["n"], cfg["r"], cfg["s"], cfg["k"]
+    n, r = cfg["n"], cfg["r"]
     blk = n * r * w
+    a, b = cfg["A"].to_scipy(), cfg["B"].to_scipy()
+    mats = (a, b.T.tocsr(), a.T.tocsr(), b)
+    diag = 8 * n if cfg["sigma"] is not None else 0
     if family == "spmm":
-        a, b = cfg["A"].to_scipy(), cfg["B"].to_scipy()
-        ops = [sell_bytes(M, w) for M in (a, b.T.tocsr(), a.T.tocsr(), b)]
-        diag = 8 * n if cfg["sigma"] is not None else 0
-        return (ops[0] + ops[1] + ops[2] + ops[3]) / 2 + 2 * (2 * blk) + diag
-    per_space = {"dots": (1 + k) * blk, "update": (k + 2) * blk, "sketch": blk + 2 * 8 * n + 8 * s * r,
-                 "whiten": 8 * s * r * d_avg}
+        if two_pass:
+            return sum(sell_bytes(M, w) for M in mats) / 2 + 2 * (2 * blk) + diag
+        return sum(csr_bytes(M, w) for M in mats) / 2 + 2 * (3 * blk) + diag
+    if two_pass:
+        per_space = {"dots": (1 + k) * blk, "update": (k + 2) * blk}
+    else:
+        per_space = {"dots": (4 * (k - 1) + 3) / k * blk, "update": 2 * blk}
+    per_space["sketch"] = blk + 2 * 8 * n + 8 * s * r
+    per_space["whiten"] = 8 * s * r * d_avg
     return 2 * per_space.get(family, 0)
 
 
-def cpu_baseline(cfg, steps):
-    """The FP64 oracle's tandem block steps/s on the same matrices (bounded sample)."""
-    from oracle import sketch as osk
-    from oracle.spksm import Space, as_operator
+def _threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        return max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg, k, s, d_conv, m_checks, ell):
+    """The FP64 oracle on the host cores, on bounded measured samples of the same solve,
+    extrapolated to the forward + adjoint time to solution (tandem block steps/s)."""
+    from oracle import sketch as osk
+    from oracle.spksm import Space, as_operator
+    from oracle.sylvester import bartels_stewart
+    n, r = cfg["n"], cfg["r"]
     A = as_operator(cfg["A"])
     BT = as_operator(cfg["B"]).T.tocsr()
-    sig = cfg["sigma"]
     su, sv = osk.space_seeds(cfg["sketch_seed"])
-    SU = osk.sparse_sign(cfg["n"], cfg["s"], 8, su)
-    SV = osk.sparse_sign(cfg["n"], cfg["s"], 8, sv)
-    opu = (lambda X: A @ X) if sig is None else (lambda X: A @ X + sig[:, None] * X)
-    U = Space(opu, SU, cfg["k"], cfg["r"], steps + 1, False)
-    V = Space(lambda X: BT @ X, SV, cfg["k"], cfg["r"], steps + 1, False)
+    SU = osk.sparse_sign(n, s, 8, su)
+    SV = osk.sparse_sign(n, s, 8, sv)
+    U = Space(lambda X: A @ X, SU, k, r, d_conv + 1, False)
+    V = Space(lambda X: BT @ X, SV, k, r, d_conv + 1, False)
+    # (1) the first block steps, as run
     U.init(cfg["C1"])
     V.init(cfg["C2"])
+    n_early = 4
     t0 = time.perf_counter()
-    for d in range(1, steps + 1):
+    for d in range(1, n_early + 1):
         U.step(d)
         V.step(d)
-    el = time.perf_counter() - t0
-    return dict(value=steps / el, unit="tandem block steps/s", cores=int(threads), kind="oracle",
-                sample=f"{steps} tandem block steps (d = 1..{steps}) of the FP64 oracle on the n = 1e6 "
-                       f"convection-diffusion pair (SpMM, truncated MGS, QR, sketch, sketched QR update); "
-                       f"{el:.1f} s; SciPy sparse products single-threaded, BLAS threads = {threads}")
+    t_early = (time.perf_counter() - t0) / n_early
+    # (2) one tandem step at the stopping step: window blocks and the sketched basis Q
+    # filled with the sizes they have there (their values do not change the operation count)
+    rng = np.random.Generator(np.random.PCG64(5))
+    dl = d_conv
+    for sp_ in (U, V):
+        for j in range(dl - k + 1, dl + 1):
+            sp_.blocks[j] = rng.standard_normal((n, r))
+        sp_.Q[:, :dl * r] = rng.standard_normal((s, dl * r)) / np.sqrt(s)
+        sp_.T[:dl * r, :dl * r] = np.eye(dl * r)
+    t0 = time.perf_counter()
+    U.step(dl)
+    V.step(dl)
+    t_late = time.perf_counter() - t0
+    # the step cost grows linearly in d through the whitening (Q has d r columns)
+    t_steps = d_conv * (t_early + t_late) / 2
+    # (3) one projected solve (Bartels-Stewart on the Schur forms) at order 400, scaled by m^3
+    m0 = 400
+    MA = np.triu(rng.standard_normal((m0, m0)), -r) + 4 * m0 * np.eye(m0)
+    MB = np.triu(rng.standard_normal((m0, m0)), -r) + 4 * m0 * np.eye(m0)
+    F = np.zeros((m0, m0))
+    F[:r, :r] = rng.standard_normal((r, r))
+    t0 = time.perf_counter()
+    bartels_stewart(MA, MB.T, F)
+    t_proj0 = time.perf_counter() - t0
+    t_proj = sum(t_proj0 * (m / m0) ** 3 for m in m_checks)
+    # (4) recovery X1 = U_d W (n x d r times d r x ell) on a slice of rows, scaled to n
+    rows = 20000
+    Ub = rng.standard_normal((rows, d_conv * r))
+    W = rng.standard_normal((d_conv * r, ell))
+    t0 = time.perf_counter()
+    _ = Ub @ W
+    t_rec = 2 * (time.perf_counter() - t0) * n / rows
+    t_solve = t_steps + t_proj + t_rec
+    t_job = 2 * t_solve
+    return dict(value=round(2 * d_conv / t_job, 3), unit="tandem block steps/s", cores=int(_threads()), kind="oracle",
+                time_to_solution_fwd_adj_s=round(t_job, 1),
+                split_s=dict(block_steps=round(t_steps, 1), projected_solves=round(t_proj, 1),
+                             recovery=round(t_rec, 1)),
+                sample=(f"FP64 oracle on the host: {n_early} tandem block steps at d = 1..{n_early} "
+                        f"({t_early:.2f} s each) and one at d = {dl} with its k = {k} window and s x {dl * r} "
+                        f"sketched basis ({t_late:.2f} s; the step cost grows linearly in d), one Bartels-Stewart "
+                        f"projected solve at order {m0} ({t_proj0:.2f} s, scaled by m^3 to the checks at "
+                        f"m = {list(m_checks)}), and the recovery product on {rows} rows scaled to n; "
+                        f"extrapolated to the forward and adjoint solves of d = {d_conv}; SciPy sparse products "
+                        f"single-threaded, BLAS threads = {_threads()}"))
 
 
 def main():
@@ -177,44 +245,20 @@ def main():
     import paper_2311_16019_amd as skr
     from workloads import make_config
 
-    cfg = make_config(WORKLOAD)  # s = 8000 (4 * 500 * r), k = 3, r = 4, tol 1e-6
+    cfg = make_config(WORKLOAD)
+    r = cfg["r"]
+    s_tts = 4 * TTS["maxit"] * r
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
     A = skr.Operator.from_csr(cfg["A"].indptr, cfg["A"].indices, cfg["A"].data, diag=cfg["sigma"])
     B = skr.Operator.from_csr(cfg["B"].indptr, cfg["B"].indices, cfg["B"].data)
     C1, C2, P1, P2 = dev(cfg["C1"]), dev(cfg["C2"]), dev(cfg["P1"]), dev(cfg["P2"])
-    win = args.window
 
-    def params(precision, profile=False):
-        return dict(k=cfg["k"], maxit=win, p=win, s=cfg["s"], tol=cfg["tol"], seed=cfg["sketch_seed"],
+    def tts_params(precision, profile=False):
+        return dict(k=TTS["k"], maxit=TTS["maxit"], p=TTS["p"], s=s_tts, tol=TTS["tol"], seed=cfg["sketch_seed"],
                     precision=precision, recover="stored", profile=profile)
 
-    wall = dict(forward=0.0, adjoint=0.0, grads=0.0, solves=0.0)
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
-    pool = None
-    if args.concurrent:
-        from concurrent.futures import ThreadPoolExecutor
-        pool = ThreadPoolExecutor(max_workers=2)
-
-    def on_stream(st, fn, *a, **kw):
-        with torch.cuda.stream(st):
-            return fn(*a, stream=st, **kw)
-
-    def one_step(precision, profile=False):
-        prm = params(precision, profile)
-        if pool is not None:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ff = pool.submit(on_stream, streams[0], skr.solve, A, B, C1, C2, **prm)
-            fa = pool.submit(on_stream, streams[1], skr.adjoint_solve, A, B, P1, P2, **prm)
-            f, a = ff.result(), fa.result()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            wall["solves"] += 1e3 * (t2 - t0)
-            wall["grads"] += 1e3 * (t3 - t2)
-            return f, a, g
+    def one_step(prm):
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         f = skr.solve(A, B, C1, C2, **prm)
         torch.cuda.synchronize()
@@ -225,188 +269,181 @@ def main():
         g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        wall["forward"] += 1e3 * (t1 - t0)
-        wall["adjoint"] += 1e3 * (t2 - t1)
-        wall["solves"] += 1e3 * (t2 - t0)
-        wall["grads"] += 1e3 * (t3 - t2)
-        return f, a, g
+        return f, a, g, dict(forward=t1 - t0, adjoint=t2 - t1, grads=t3 - t2, total=t3 - t0)
 
-    # warm-up with every kernel family timed: the per-family table and the roofline kernel,
-    # the single-kernel streaming family (spmm, dots, update) with the most time.  The timed
-    # steps record events around that family's launches only (events around every launch of
-    # every family lengthen the block steps by about a fifth).
+    def family_table(results, w, k, d_avg, s, two_pass):
+        fam = {}
+        for res in results:
+            for key, (nl, ms) in res.kernels.items():
+                L, M = fam.get(key, (0, 0.0))
+                fam[key] = (L + nl, M + ms)
+        out = {}
+        for key, (nl, ms) in fam.items():
+            out[key] = dict(launches=nl, avg_us=round(1000.0 * ms / nl, 2))
+            b = algorithmic_bytes(key, cfg, w, k, d_avg, s, two_pass)
+            if b:
+                out[key]["gbs"] = round(b / (ms / nl * 1e-3) / 1e9, 1)
+        return fam, out
+
+    two_pass_tts = r <= 4 and TTS["k"] <= 3
+
+    # ---- FP64 time to solution: warm-up with every kernel family timed (the family table and
+    # the roofline kernel: the single-kernel streaming family with the most time), then the
+    # timed steps with events around that family's launches only
     fam_warm = {}
     for _ in range(max(1, args.warmup)):
-        f, a, _ = one_step(args.precision, profile=True)
-        f_warm = f  # the comparison legs below time every family too, so they compare with this
-        for res in (f, a):
-            for k, (nl, ms) in res.kernels.items():
-                L, M = fam_warm.get(k, (0, 0.0))
-                fam_warm[k] = (L + nl, M + ms)
+        f, a, _, _ = one_step(tts_params("fp64", profile=True))
+        fam_warm, fam_warm_tab = family_table((f, a), 8, TTS["k"], f.iters / 2, s_tts, two_pass_tts)
     single = [k for k in ("spmm", "dots", "update") if k in fam_warm]
     dominant = max(single, key=lambda k: fam_warm[k][1])
 
-    torch.cuda.synchronize()
-    for key in wall:
-        wall[key] = 0.0
-    t0 = time.perf_counter()
+    wall = dict(forward=0.0, adjoint=0.0, grads=0.0)
+    split = dict(steps=0.0, proj=0.0, recover=0.0)
     fam = {}
     steps_done = 0
-    split = dict(steps=0.0, proj=0.0, recover=0.0)
-    last = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for _ in range(args.steps):
-        f, a, g = one_step(args.precision, profile=dominant)
+        f, a, g, tm = one_step(tts_params("fp64", profile=dominant))
+        for key in wall:
+            wall[key] += tm[key]
         for res in (f, a):
             steps_done += res.iters
             split["steps"] += res.ms_steps
             split["proj"] += res.ms_proj
             split["recover"] += res.ms_recover
-            for k, (nl, ms) in res.kernels.items():
-                L, M = fam.get(k, (0, 0.0))
-                fam[k] = (L + nl, M + ms)
-        last = (f, a, g)
+            for key, (nl, ms) in res.kernels.items():
+                L, M = fam.get(key, (0, 0.0))
+                fam[key] = (L + nl, M + ms)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_step = 1000.0 * el / args.steps
     value = steps_done / el
+    f64, a64, g64 = f, a, g
+    tr_f = skr.true_residual(A, B, f.X1, f.X2, C1, C2)
+    tr_a = skr.true_residual(A, B, a.X1, a.X2, P1, P2, adjoint=True)
 
-    f, a, g = last
-    true_res = skr.true_residual(A, B, f.X1, f.X2, C1, C2)
-    w = 4 if args.precision == "mixed" else 8
     nl, ms = fam[dominant]
-    d_avg = (win + 1) / 2.0
-    per_launch = algorithmic_bytes(dominant, cfg, w, d_avg)
+    d_avg = f.iters / 2.0
+    per_launch = algorithmic_bytes(dominant, cfg, 8, TTS["k"], d_avg, s_tts, two_pass_tts)
     achieved = per_launch / (ms / nl * 1e-3) / 1e9
-    rec = measured_traffic(dominant, args.precision)
+    rec = measured_traffic(dominant, "fp64")
     roofline = dict(kernel=dominant, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=int(rec["bytes_per_launch"]) if rec else None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=int(rec["bytes_per_launch"]) if rec else None,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
-    families = {}  # from the warm-up step(s), every family timed
-    for k, v in fam_warm.items():
-        b = algorithmic_bytes(k, cfg, w, d_avg)
-        families[k] = dict(launches=v[0], avg_us=round(1000.0 * v[1] / v[0], 2))
-        if b:
-            families[k]["gbs"] = round(b / (v[1] / v[0] * 1e-3) / 1e9, 1)
 
-    out = dict(metric="Krylov tandem block steps/s at n=1M (forward + adjoint s-PKSM)", value=round(value, 2),
-               unit="block steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32+f64" if args.precision == "mixed"
-               else "f64", data="synthetic",
-               config=dict(workload="upwind convection-diffusion 1000x1000 pair (n=1e6), r=4, k=3, s=8000, "
-                                    f"{win} block steps per solve, forward + adjoint, stored-basis recovery",
-                           n=cfg["n"], r=cfg["r"], k=cfg["k"], s=cfg["s"], window=win, precision=args.precision),
-               roofline=roofline, kernel_families=families,
-               kernel_families_from="warm-up step, every kernel family timed (the timed steps time the roofline "
-                                    "kernel's family only)",
+    def solve_info(res, tr):
+        return dict(iters=res.iters, status=res.status, rho_rel=res.rho_rel, true_residual=tr, ell=res.ell,
+                    history=[[d, float(f"{x:.3e}")] for d, x in res.history], projected=res.proj,
+                    time_split_ms=dict(block_steps=round(res.ms_steps, 1), projected_solves=round(res.ms_proj, 1),
+                                       recovery=round(res.ms_recover, 1)))
+
+    tts = dict(forward_s=round(wall["forward"] / args.steps, 3), adjoint_s=round(wall["adjoint"] / args.steps, 3),
+               grads_s=round(wall["grads"] / args.steps, 4),
+               passed=bool(tr_f <= TTS["tol"] and tr_a <= TTS["tol"]),
+               forward=solve_info(f, tr_f), adjoint=solve_info(a, tr_a))
+
+    out = dict(metric="time-to-rel-residual 1e-6 and Krylov block steps/s at n=1M; fwd+adjoint vs FP64",
+               value=round(value, 2), unit="tandem block steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(ms_step, 1), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload=f"upwind convection-diffusion 1000x1000 pair (n=1e6), r=4, forward + adjoint "
+                                    f"s-PKSM to relative residual 1e-6, k={TTS['k']}, p={TTS['p']}, "
+                                    f"maxit={TTS['maxit']}, s={s_tts}, sparse sign embedding, stored-basis recovery",
+                           n=cfg["n"], r=r, k=TTS["k"], p=TTS["p"], maxit=TTS["maxit"], s=s_tts, tol=TTS["tol"]),
+               time_to_solution=tts,
+               time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 1),
+                                  projected_solves=round(split["proj"] / args.steps, 1),
+                                  recovery=round(split["recover"] / args.steps, 1),
+                                  grads=round(1000.0 * wall["grads"] / args.steps, 2)),
                block_steps_per_s=round(steps_done / (split["steps"] * 1e-3), 1),
-               time_split_ms=dict(block_steps=round(split["steps"] / args.steps, 2),
-                                  projected_solves=round(split["proj"] / args.steps, 2),
-                                  recovery=round(split["recover"] / args.steps, 2),
-                                  solves_wall=round(wall["solves"] / args.steps, 2),
-                                  grads_wall=round(wall["grads"] / args.steps, 2)),
-               schedule="forward and adjoint concurrent" if args.concurrent else "forward, then adjoint",
-               forward=dict(iters=f.iters, rho_rel=f.rho_rel, true_residual=true_res, ell=f.ell, status=f.status,
-                            projected=f.proj),
-               adjoint=dict(iters=a.iters, rho_rel=a.rho_rel, ell=a.ell, projected=a.proj))
-    if not args.no_fp64_compare and args.precision == "mixed":
-        one_step("fp64", profile=dominant)  # warm-up: FP64 workspaces differ from the mixed ones
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        f64, a64, _ = one_step("fp64", profile=dominant)  # timed as the mixed steps are
-        torch.cuda.synchronize()
-        el64 = time.perf_counter() - t1
-        out["fp64_step"] = dict(ms=round(1000.0 * el64, 2), block_steps_per_s=round((f64.iters + a64.iters) / el64, 2),
-                                speedup_mixed_over_fp64=round(1000.0 * el64 / ms_step, 3),
-                                rho_rel=f64.rho_rel,
-                                true_residual=skr.true_residual(A, B, f64.X1, f64.X2, C1, C2),
-                                time_split_ms=dict(block_steps=round(f64.ms_steps + a64.ms_steps, 2),
-                                                   projected_solves=round(f64.ms_proj + a64.ms_proj, 2),
-                                                   recovery=round(f64.ms_recover + a64.ms_recover, 2)),
-                                projected=dict(forward=f64.proj, adjoint=a64.proj))
-    # Algorithm 2 (t-PKSM: the same block steps with no embedding) on the same forward
-    # problem and window, for comparison with s-PKSM
-    if not args.no_tpksm:
-        out["tpksm_forward"] = tpksm_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True))
-    if not args.no_sorth:
-        out["sketched_orth_forward"] = sorth_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True), f_warm)
-    if not args.no_srht:
-        out["srht_forward"] = srht_leg(skr, torch, A, B, C1, C2, params(args.precision, profile=True), f_warm)
-    if not args.no_lyapunov:
-        out["lyapunov_forward"] = lyapunov_leg(skr, torch, A, C1, params(args.precision, profile=True), f_warm)
+               roofline=roofline, kernel_families=fam_warm_tab,
+               kernel_families_from="FP64 warm-up step, every kernel family timed (the timed steps time the "
+                                    "roofline kernel's family only)")
+
+    # ---- mixed precision at the same tolerance (FP32 bulk: operator values, basis, products)
+    if not args.no_mixed:
+        one_step(tts_params("mixed"))  # warm-up: the mixed workspaces differ from the FP64 ones
+        fm, am, gm, tmm = one_step(tts_params("mixed"))
+        trm_f = skr.true_residual(A, B, fm.X1, fm.X2, C1, C2)
+        trm_a = skr.true_residual(A, B, am.X1, am.X2, P1, P2, adjoint=True)
+        gerr = {k2: float(torch.linalg.norm(gm[k2] - g64[k2]) / torch.linalg.norm(g64[k2]))
+                for k2 in ("dC1", "dC2", "dP1", "dP2")}
+        t64 = wall["forward"] / args.steps + wall["adjoint"] / args.steps
+        tmix = tmm["forward"] + tmm["adjoint"]
+        passed = bool(trm_f <= TTS["tol"] and trm_a <= TTS["tol"])
+        out["mixed"] = dict(forward_s=round(tmm["forward"], 3), adjoint_s=round(tmm["adjoint"], 3),
+                            grads_s=round(tmm["grads"], 4), passed=passed,
+                            forward=solve_info(fm, trm_f), adjoint=solve_info(am, trm_a),
+                            grad_rel_err_vs_fp64=gerr,
+                            block_steps_per_s=round((fm.iters + am.iters) / ((fm.ms_steps + am.ms_steps) * 1e-3), 1))
+        out["mixed_vs_fp64"] = dict(
+            speedup_fwd_adj=round(t64 / tmix, 3),
+            both_at_true_residual_1e_6=bool(passed and tts["passed"]),
+            mixed_faster_at_same_residual=bool(passed and tts["passed"] and tmix < t64),
+            gradients_within_1e_4=bool(max(gerr.values()) <= 1e-4))
+
+    # ---- fixed-window block-step throughput with the workload's own k = 3 (no projected solve
+    # inside the window); this is the two-pass block step of the round-one benchmark
+    win = args.window
+
+    def win_params(precision, profile=True, **extra):
+        prm = dict(k=cfg["k"], maxit=win, p=win, s=cfg["s"], tol=0.0, seed=cfg["sketch_seed"], precision=precision,
+                   recover="stored", profile=profile)
+        prm.update(extra)
+        return prm
+
+    f_win = None
+    if not args.no_window:
+        legs = {}
+        for precision in ("fp64", "mixed"):
+            w = 8 if precision == "fp64" else 4
+            skr.solve(A, B, C1, C2, **win_params(precision))  # warm-up
+            torch.cuda.synchronize()
+            fw = skr.solve(A, B, C1, C2, **win_params(precision))
+            torch.cuda.synchronize()
+            _, tab = family_table((fw,), w, cfg["k"], (win + 1) / 2.0, cfg["s"], r <= 4 and cfg["k"] <= 3)
+            legs[precision] = dict(block_steps_per_s=round(fw.iters / (fw.ms_steps * 1e-3), 1),
+                                   block_steps_ms=round(fw.ms_steps, 2), kernel_families=tab)
+            if precision == "mixed":
+                f_win = fw
+        out["window_k3"] = dict(window=win, k=cfg["k"], s=cfg["s"], note="forward solve, every kernel family timed",
+                                **legs)
+    if f_win is not None:
+        if not args.no_tpksm:
+            out["tpksm_forward"] = leg(skr, torch, A, B, C1, C2, win_params("mixed", sketch="none"), f_win)
+        if not args.no_sorth:
+            out["sketched_orth_forward"] = leg(skr, torch, A, B, C1, C2, win_params("mixed", orth="sketched"), f_win)
+        if not args.no_srht:
+            out["srht_forward"] = leg(skr, torch, A, B, C1, C2, win_params("mixed", sketch="srht"), f_win)
+        if not args.no_lyapunov:
+            out["lyapunov_forward"] = leg(skr, torch, A, None, C1, None, win_params("mixed"), f_win)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        m_checks = [d * r for d, _ in f64.history]
+        out["cpu_baseline"] = cpu_baseline(cfg, TTS["k"], s_tts, f64.iters, m_checks, f64.ell)
     print(json.dumps(out))
 
 
-def sorth_leg(skr, torch, A, B, C1, C2, prm, f_euc):
-    """The forward solve with the truncated orthogonalisation in the sketched inner product
-    (appendix A) on the same problem and window, beside the Euclidean block steps."""
-    prm["orth"] = "sketched"
-    skr.solve(A, B, C1, C2, **prm)  # warm-up
+def leg(skr, torch, A, B, C1, C2, prm, f_ref):
+    """A comparison solve on the same problem and window (t-PKSM, the sketched-inner-product
+    orthogonalisation, the DCT embedding, or the Lyapunov solve when B is None), beside the
+    mixed Euclidean sparse-sign forward solve's block steps."""
+    run = (lambda: skr.lyap_solve(A, C1, **prm)) if B is None else (lambda: skr.solve(A, B, C1, C2, **prm))
+    run()  # warm-up (also builds the DCT plans)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    fs = skr.solve(A, B, C1, C2, **prm)
+    fs = run()
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    return dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fs.iters / el, 1), iters=fs.iters,
-                time_split_ms=dict(block_steps=round(fs.ms_steps, 2), projected_solves=round(fs.ms_proj, 2),
-                                   recovery=round(fs.ms_recover, 2)),
-                euclidean_forward_block_steps_ms=round(f_euc.ms_steps, 2),
-                kernel_families={k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in fs.kernels.items()},
-                rho_rel=fs.rho_rel, true_residual=skr.true_residual(A, B, fs.X1, fs.X2, C1, C2),
-                projected=fs.proj)
-
-
-def srht_leg(skr, torch, A, B, C1, C2, prm, f_sparse):
-    """The forward solve with the subsampled randomized DCT embedding of the paper's
-    experiments (Sec. 6) instead of the sparse sign one, same problem, s and window."""
-    prm["sketch"] = "srht"
-    skr.solve(A, B, C1, C2, **prm)  # warm-up (also builds the sampled-row plans)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fs = skr.solve(A, B, C1, C2, **prm)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    fam = {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in fs.kernels.items()}
-    return dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fs.iters / el, 1), iters=fs.iters,
-                time_split_ms=dict(block_steps=round(fs.ms_steps, 2), projected_solves=round(fs.ms_proj, 2),
-                                   recovery=round(fs.ms_recover, 2)),
-                sparse_sign_forward_block_steps_ms=round(f_sparse.ms_steps, 2), kernel_families=fam,
-                rho_rel=fs.rho_rel, true_residual=skr.true_residual(A, B, fs.X1, fs.X2, C1, C2),
-                projected=fs.proj)
-
-
-def lyapunov_leg(skr, torch, A, C1, prm, f_sylv):
-    """The Lyapunov specialisation A X + X A^T = C1 C1^T on the same operator and window: one
-    Krylov space instead of two (compare its block-step time with the Sylvester solve's)."""
-    skr.lyap_solve(A, C1, **prm)  # warm-up
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fl = skr.lyap_solve(A, C1, **prm)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    return dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fl.iters / el, 1),
-                time_split_ms=dict(block_steps=round(fl.ms_steps, 2), projected_solves=round(fl.ms_proj, 2),
-                                   recovery=round(fl.ms_recover, 2)),
-                sylvester_forward_block_steps_ms=round(f_sylv.ms_steps, 2), rho_rel=fl.rho_rel,
-                projected=fl.proj)
-
-
-def tpksm_leg(skr, torch, A, B, C1, C2, prm_t):
-    """Algorithm 2 (t-PKSM: the same block steps with no embedding) on the same forward
-    problem and window, for comparison with s-PKSM."""
-    prm_t["sketch"] = "none"
-    skr.solve(A, B, C1, C2, **prm_t)  # warm-up
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ft = skr.solve(A, B, C1, C2, **prm_t)
-    torch.cuda.synchronize()
-    elt = time.perf_counter() - t1
-    return dict(ms=round(1000.0 * elt, 2), block_steps_per_s=round(ft.iters / elt, 1),
-                time_split_ms=dict(block_steps=round(ft.ms_steps, 2), projected_solves=round(ft.ms_proj, 2),
-                                   recovery=round(ft.ms_recover, 2)),
-                rho_rel=ft.rho_rel, true_residual=skr.true_residual(A, B, ft.X1, ft.X2, C1, C2), projected=ft.proj)
+    out = dict(ms=round(1000.0 * el, 2), block_steps_per_s=round(fs.iters / (fs.ms_steps * 1e-3), 1),
+               time_split_ms=dict(block_steps=round(fs.ms_steps, 2), projected_solves=round(fs.ms_proj, 2),
+                                  recovery=round(fs.ms_recover, 2)),
+               reference_block_steps_ms=round(f_ref.ms_steps, 2),
+               kernel_families={k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in fs.kernels.items()},
+               rho_rel=fs.rho_rel, projected=fs.proj)
+    if B is not None:
+        out["true_residual"] = skr.true_residual(A, B, fs.X1, fs.X2, C1, C2)
+    return out
 
 
 if __name__ == "__main__":

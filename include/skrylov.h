@@ -221,6 +221,14 @@ SKR_API int skr_true_residual(skr_op A, skr_op B, const double* X1, const double
                       const double* C1, const double* C2, int64_t r, void* stream, double* rel);
 
 /*
+ * The same for the transposed (adjoint) equation: ||A^T L + L B^T - G1 G2^T||_F / ||G1 G2^T||_F
+ * of L = L1 L2^T (the factors skr_adjoint_solve returns), from QR factorisations of
+ * [A^T L1, L1, -G1] and [L2, B L2, G2].  Arguments and layouts as for skr_true_residual.
+ */
+SKR_API int skr_true_residual_adjoint(skr_op A, skr_op B, const double* L1, const double* L2, int64_t ell,
+                      const double* G1, const double* G2, int64_t r, void* stream, double* rel);
+
+/*
  * Loss and gradients of L = tr(P1^T X P2), X = X1 X2^T, given the adjoint factors
  * Lam = L1 L2^T of A^T Lam + Lam B^T = P1 P2^T (dL = <Lam, dC1 C2^T + C1 dC2^T - dA X>):
  *   dC1 = L1 (L2^T C2)   n1 x r        dC2 = L2 (L1^T C1)   n2 x r

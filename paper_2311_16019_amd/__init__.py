@@ -239,12 +239,14 @@ def lyap_solve(A: Operator, C, stream=None, **params) -> Result:
         lib.skr_result_destroy(h)
 
 
-def true_residual(A: Operator, B: Operator, X1, X2, C1, C2, stream=None) -> float:
-    """``||A X + X B - C1 C2^T||_F / ||C1 C2^T||_F`` for ``X = X1 X2^T`` (on the GPU)."""
+def true_residual(A: Operator, B: Operator, X1, X2, C1, C2, stream=None, adjoint=False) -> float:
+    """``||A X + X B - C1 C2^T||_F / ||C1 C2^T||_F`` for ``X = X1 X2^T`` (on the GPU);
+    with ``adjoint=True`` the transposed equation's ``||A^T X + X B^T - C1 C2^T||_F / ||C1 C2^T||_F``."""
     lib = _lib.load()
     ell, r = X1.shape[1], C1.shape[1]
     out = ctypes.c_double()
-    _lib.check(lib.skr_true_residual(A._h, B._h, _dev_ptr(X1, "X1", (A.n, ell)), _dev_ptr(X2, "X2", (B.n, ell)), ell,
+    entry = lib.skr_true_residual_adjoint if adjoint else lib.skr_true_residual
+    _lib.check(entry(A._h, B._h, _dev_ptr(X1, "X1", (A.n, ell)), _dev_ptr(X2, "X2", (B.n, ell)), ell,
                                      _dev_ptr(C1, "C1", (A.n, r)), _dev_ptr(C2, "C2", (B.n, r)), r, _stream(stream),
                                      ctypes.byref(out)))
     return out.value

@@ -62,6 +62,7 @@ SIGNATURES = {
     "skr_result_proj_stats": (_i32, [_vp, _pi32, _pi32, _pi32, _pf64]),
     "skr_result_destroy": (_i32, [_vp]),
     "skr_true_residual": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),
+    "skr_true_residual_adjoint": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),
     "skr_pairing_grads": (_i32, [_i64, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                                  _pf64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "skr_pairing_grads_noalloc": (_i32, [_i64, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp,

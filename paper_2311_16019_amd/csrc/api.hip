@@ -336,8 +336,15 @@ int skr_result_destroy(skr_result res) {
   return SKR_OK;
 }
 
-int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, int64_t ell, const double* C1,
-                      const double* C2, int64_t r, void* stream, double* rel) {
+}  // extern "C"
+
+namespace {
+
+// ||opA(A) X + X opB(B)^T... evaluated as ||[A' X1, X1, -C1] [X2, B' X2, C2]^T||_F / ||C1 C2^T||_F
+// with A' = A (ta = 0) or A^T (ta = 1) applied to X1 and B' = B^T (tb = 1, the forward
+// equation's X B = X1 (B^T X2)^T) or B (tb = 0, the adjoint's L B^T = L1 (B L2)^T).
+int true_residual_impl(skr_op A, int ta, skr_op B, int tb, const double* X1, const double* X2, int64_t ell,
+                       const double* C1, const double* C2, int64_t r, void* stream, double* rel) {
   return guarded([&] {
     check_op(A);
     check_op(B);
@@ -355,9 +362,9 @@ int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, in
     hipLaunchKernelGGL(rm_to_cm_kernel, dim3(grid((int64_t)n2 * L)), dim3(256), 0, st, n2, L, X2, 1.0, Rm.p, n2);
     hipLaunchKernelGGL(rm_to_cm_kernel, dim3(grid((int64_t)n2 * R)), dim3(256), 0, st, n2, R, C2, 1.0, Rm.p + (size_t)2 * L * n2, n2);
     check_launch("rm_to_cm");
-    hipLaunchKernelGGL(spmm_wide_kernel, dim3(grid((int64_t)n1 * L)), dim3(256), 0, st, csr_view<double>(A, 0), L,
+    hipLaunchKernelGGL(spmm_wide_kernel, dim3(grid((int64_t)n1 * L)), dim3(256), 0, st, csr_view<double>(A, ta), L,
                        Lm.p + (size_t)L * n1, Lm.p, nullptr, n1);
-    hipLaunchKernelGGL(spmm_wide_kernel, dim3(grid((int64_t)n2 * L)), dim3(256), 0, st, csr_view<double>(B, 1), L,
+    hipLaunchKernelGGL(spmm_wide_kernel, dim3(grid((int64_t)n2 * L)), dim3(256), 0, st, csr_view<double>(B, tb), L,
                        Rm.p, Rm.p + (size_t)L * n2, nullptr, n2);
     check_launch("spmm_wide");
     // ||C1 C2^T||_F via the same route on the r-column factors
@@ -379,6 +386,20 @@ int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, in
     *rel = std::sqrt(h[0] / h[1]);
     return SKR_OK;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+int skr_true_residual(skr_op A, skr_op B, const double* X1, const double* X2, int64_t ell, const double* C1,
+                      const double* C2, int64_t r, void* stream, double* rel) {
+  return true_residual_impl(A, 0, B, 1, X1, X2, ell, C1, C2, r, stream, rel);
+}
+
+int skr_true_residual_adjoint(skr_op A, skr_op B, const double* L1, const double* L2, int64_t ell, const double* G1,
+                              const double* G2, int64_t r, void* stream, double* rel) {
+  return true_residual_impl(A, 1, B, 0, L1, L2, ell, G1, G2, r, stream, rel);
 }
 
 }  // extern "C"

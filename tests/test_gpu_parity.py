@@ -93,6 +93,26 @@ def test_true_residual_matches_oracle_evaluation():
     assert abs(tr_gpu / tr_orc - 1) <= 1e-8
 
 
+def test_true_residual_adjoint_matches_oracle_evaluation():
+    """The adjoint equation's residual A^T L + L B^T - G1 G2^T of an adjoint solve, on a
+    nonsymmetric pair with a diagonal term (the oracle evaluates it with A^T and B^T)."""
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=31, r=3)
+    sig = np.linspace(0.0, 2.0, cfg["n"])
+    A = skr.Operator.from_csr(cfg["A"].indptr, cfg["A"].indices, cfg["A"].data, diag=sig)
+    B = skr.Operator.from_csr(cfg["B"].indptr, cfg["B"].indices, cfg["B"].data)
+    G1, G2 = to_dev(cfg["C1"]), to_dev(cfg["C2"])
+    a = skr.adjoint_solve(A, B, G1, G2, k=3, maxit=20, p=10, s=480, tol=0.0, seed=3)
+    tr_gpu = skr.true_residual(A, B, a.X1, a.X2, G1, G2, adjoint=True)
+    At = cfg["A"].to_scipy().T.tocsr()
+    Bt = cfg["B"].to_scipy().T.tocsr()
+    tr_orc = oracle_true_residual(At, Bt, cfg["C1"], cfg["C2"], a.X1.cpu().numpy(), a.X2.cpu().numpy(), sigma=sig)
+    assert abs(tr_gpu / tr_orc - 1) <= 1e-8
+    # and the forward evaluation of the same factors differs (the operators are nonsymmetric)
+    tr_fwd = skr.true_residual(A, B, a.X1, a.X2, G1, G2)
+    assert abs(tr_fwd / tr_orc - 1) > 1e-3
+
+
 @pytest.mark.parametrize("m", [4, 5, 16])
 def test_tiny_and_single_tile_sizes(m):
     """n = 16, 25, 256: fewer rows than one tile, and exactly one tile."""
