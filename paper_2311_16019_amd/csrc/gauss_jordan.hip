@@ -15,8 +15,9 @@
 // Launch b runs one workgroup that applies E_{b-1} to the columns of panel b and then
 // eliminates panel b in registers (one barrier per column), and many workgroups that apply
 // E_{b-1} to all remaining columns: n / NB + 1 launches for the whole elimination.  The
-// panel workgroup has one wavefront per SIMD: the per-column pivot search and broadcast
-// are latency chains, and more wavefronts would only time-share the SIMDs on them.
+// panel workgroup has one wavefront per SIMD up to order 1024 and two above: the
+// per-column pivot search and broadcast are latency chains that more wavefronts would only
+// time-share, but the panel width is bounded by the rows each thread holds in registers.
 #include <climits>
 #include <type_traits>
 #include <cmath>
@@ -27,8 +28,6 @@ namespace skr {
 namespace dense {
 namespace {
 
-constexpr int GJ_T = 256;         // threads per workgroup: one wavefront per SIMD
-constexpr int GJ_W = GJ_T / 64;   // wavefronts per workgroup
 constexpr int GJ_CW = 4;          // columns per strip of an update workgroup
 constexpr int GJ_MAXUPD = 511;    // update workgroups per launch
 
@@ -112,40 +111,47 @@ __device__ inline K wave_max_key(K v) {
   return m;
 }
 
-// One row set per thread: row(q) = threadIdx.x + GJ_T q.
-template <int RPT>
-__device__ inline int row_of(int q) { return threadIdx.x + GJ_T * q; }
+// One row set per thread: row(q) = threadIdx.x + TG q.
+template <int RPT, int TG>
+__device__ inline int row_of(int q) { return threadIdx.x + TG * q; }
+
+// Whether the panel workgroup stages the previous panel in LDS (at most 128 KiB).
+template <int RPT, int NB, int TG>
+constexpr bool gj_stage() { return TG * RPT * NB * 8 <= 128 * 1024; }
 
 // Panel workgroup of launch b: apply E_{b-1} to the columns K_b, then eliminate K_b.
-template <int RPT, int NB>
+// TG threads per workgroup (one or two wavefronts per SIMD); the previous panel's columns
+// are staged in LDS when they fit (STAGE), else read from global memory (L2) column by column.
+template <int RPT, int NB, int TG>
 __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   __shared__ int pl[NB];
   __shared__ int pivl[NB];
   __shared__ double amat[NB][NB];
-  using Key = std::conditional_t<(GJ_T * RPT <= 2048), uint32_t, uint64_t>;
-  __shared__ Key ckey[2][GJ_W];
-  __shared__ double crow[2][GJ_W][NB];
-  __shared__ double red[GJ_W];
+  using Key = std::conditional_t<(TG * RPT <= 2048), uint32_t, uint64_t>;
+  __shared__ Key ckey[2][(TG / 64)];
+  __shared__ double crow[2][(TG / 64)][NB];
+  __shared__ double red[(TG / 64)];
   const int tid = threadIdx.x, wv = tid / 64;
   if (g.b == g.nblk) {  // final launch: log|det A| = sum of log|pivot|, in a fixed order
     if (g.logabsdet && g.want_logdet) {
       double l = 0.0;
-      for (int k = tid; k < g.n; k += GJ_T) l += (g.pivabs[k] > 0.0) ? log(g.pivabs[k]) : 0.0;
+      for (int k = tid; k < g.n; k += TG) l += (g.pivabs[k] > 0.0) ? log(g.pivabs[k]) : 0.0;
       l = wave_sum(l);
       if (tid % 64 == 0) red[wv] = l;
       __syncthreads();
       if (tid == 0) {
         double t = 0.0;
-        for (int w = 0; w < GJ_W; ++w) t += red[w];
+        for (int w = 0; w < (TG / 64); ++w) t += red[w];
         *g.logabsdet = t;
       }
     }
     return;
   }
   const int k0 = g.c0 + g.b * NB, nbc = min(NB, g.c0 + g.npiv - k0);
-  constexpr int ROWS = GJ_T * RPT;
+  constexpr int ROWS = TG * RPT;
   const int kp0 = k0 - NB;
-  if (g.b > 0) {
+  constexpr bool STAGE = gj_stage<RPT, NB, TG>();
+  if (STAGE && g.b > 0) {
     // The previous panel's columns S(:, K_{b-1}) (panel b-1 is always full) are staged in
     // LDS by direct global-to-LDS loads, issued before this panel's own loads so that both
     // sets are in flight together: sl[t * ROWS + row].  One instruction moves 128 rows of a
@@ -156,7 +162,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     const int lane = tid % 64;
     const bool wide = g.wide != 0;
     const int rows_per = wide ? 128 : 32, nch = (g.n + rows_per - 1) / rows_per;
-    for (int e = wv; e < NB * nch; e += GJ_W) {
+    for (int e = wv; e < NB * nch; e += (TG / 64)) {
       const int t = e / nch, j = e % nch;
       const double* col = g.S + (size_t)(kp0 + t) * g.ld;
       auto* dst = (__attribute__((address_space(3))) void*)(sl + t * ROWS + rows_per * j);
@@ -172,7 +178,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   bool elig[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int row = row_of<RPT>(q);
+    const int row = row_of<RPT, TG>(q);
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[q][c] = (row < g.n && c < nbc) ? g.S[row + (size_t)(k0 + c) * g.ld] : 0.0;
     elig[q] = (row < g.n) && (g.used[row] == 0);
@@ -185,7 +191,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     int tp[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int row = row_of<RPT>(q);
+      const int row = row_of<RPT, TG>(q);
       tp[q] = -1;
       for (int t = 0; t < NB; ++t)
         if (pl[t] == row) tp[q] = t;
@@ -197,8 +203,14 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
 #pragma unroll 2
     for (int t = 0; t < NB; ++t) {
       double sv[RPT];
+      if constexpr (STAGE) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) sv[q] = sl[t * ROWS + row_of<RPT>(q)];
+        for (int q = 0; q < RPT; ++q) sv[q] = sl[t * ROWS + row_of<RPT, TG>(q)];
+      } else {  // column t of the previous panel, written by the previous launch (in L2)
+        const double* col = g.S + (size_t)(kp0 + t) * g.ld;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) sv[q] = (row_of<RPT, TG>(q) < g.n) ? col[row_of<RPT, TG>(q)] : 0.0;
+      }
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const double a = amat[t][c];
@@ -213,7 +225,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
         for (int c = 0; c < NB; ++c) x[q][c] -= amat[tp[q]][c];
   }
   // Eliminate the panel's columns: per column one pivot search (keys reduced within each
-  // wavefront, then over the GJ_W candidates published in LDS) and one barrier; the LDS
+  // wavefront, then over the (TG / 64) candidates published in LDS) and one barrier; the LDS
   // records are double-buffered so the next column's writes cannot race this column's reads.
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
@@ -222,13 +234,13 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     Key key = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const Key kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT>(q), Key{}) : Key{0};
+      const Key kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT, TG>(q), Key{}) : Key{0};
       key = kq > key ? kq : key;
     }
     const Key wkey = wave_max_key(key);  // uniform over the wavefront
     if (wkey != 0) {
-      const int wr = key_row(wkey), wq = wr / GJ_T;  // wq uniform: scalar branches below
-      if (wr % GJ_T == tid) {
+      const int wr = key_row(wkey), wq = wr / TG;  // wq uniform: scalar branches below
+      if (wr % TG == tid) {
         ckey[buf][wv] = wkey;
 #pragma unroll
         for (int q = 0; q < RPT; ++q)
@@ -243,7 +255,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     Key gk = 0;
     int gw = 0;
 #pragma unroll
-    for (int w = 0; w < GJ_W; ++w) {
+    for (int w = 0; w < (TG / 64); ++w) {
       const Key kw = ckey[buf][w];
       if (kw > gk) { gk = kw; gw = w; }
     }
@@ -266,8 +278,8 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
         if (cc != c) x[q][cc] -= f * ps[cc];
       x[q][c] = -f * inv;
     }
-    if (gr % GJ_T == tid) {
-      const int gq = gr / GJ_T;
+    if (gr % TG == tid) {
+      const int gq = gr / TG;
 #pragma unroll
       for (int q = 0; q < RPT; ++q)
         if (q == gq) {
@@ -293,7 +305,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int row = row_of<RPT>(q);
+    const int row = row_of<RPT, TG>(q);
     if (row >= g.n) continue;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
@@ -303,7 +315,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
 
 // Update workgroup of launch b >= 1: apply E_{b-1} to its strips of columns outside
 // K_{b-1} and K_b.
-template <int RPT, int NB>
+template <int RPT, int NB, int TG>
 __device__ void update_workgroup(const GjArgs& g) {
   __shared__ int pl[NB];
   __shared__ double am[NB][GJ_CW];
@@ -316,7 +328,7 @@ __device__ void update_workgroup(const GjArgs& g) {
   int tp[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int row = row_of<RPT>(q);
+    const int row = row_of<RPT, TG>(q);
 #pragma unroll
     for (int t = 0; t < NB; ++t)
       s[q][t] = (row < g.n && t < nbp) ? g.S[row + (size_t)(kp0 + t) * g.ld] : 0.0;
@@ -328,7 +340,7 @@ __device__ void update_workgroup(const GjArgs& g) {
   const int nstrips = (g.cend - g.c0 + GJ_CW - 1) / GJ_CW;
   for (int strip = blockIdx.x - 1; strip < nstrips; strip += g.nupd) {
     const int j0 = g.c0 + strip * GJ_CW;
-    for (int e = tid; e < NB * GJ_CW; e += GJ_T) {
+    for (int e = tid; e < NB * GJ_CW; e += TG) {
       const int t = e / GJ_CW, jj = e % GJ_CW, j = j0 + jj;
       am[t][jj] = (t < nbp && !skip(j)) ? g.S[pl[t] + (size_t)j * g.ld] : 0.0;
     }
@@ -342,7 +354,7 @@ __device__ void update_workgroup(const GjArgs& g) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         acc[q] = 0.0;
-        v[q] = (row_of<RPT>(q) < g.n) ? col[row_of<RPT>(q)] : 0.0;
+        v[q] = (row_of<RPT, TG>(q) < g.n) ? col[row_of<RPT, TG>(q)] : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
@@ -352,7 +364,7 @@ __device__ void update_workgroup(const GjArgs& g) {
       }
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int row = row_of<RPT>(q);
+        const int row = row_of<RPT, TG>(q);
         if (row >= g.n) continue;
         double w = v[q] + acc[q];
         if (tp[q] >= 0) w -= am[tp[q]][jj];
@@ -363,11 +375,11 @@ __device__ void update_workgroup(const GjArgs& g) {
   }
 }
 
-template <int RPT, int NB>
-__global__ void __launch_bounds__(GJ_T) gj_step_kernel(GjArgs g) {
-  extern __shared__ double sl[];  // GJ_T * RPT * NB doubles, panel workgroup only
-  if (blockIdx.x == 0) panel_workgroup<RPT, NB>(g, sl);
-  else if (g.b > 0) update_workgroup<RPT, NB>(g);
+template <int RPT, int NB, int TG>
+__global__ void __launch_bounds__(TG) gj_step_kernel(GjArgs g) {
+  extern __shared__ double sl[];  // TG * RPT * NB doubles when staged, panel workgroup only
+  if (blockIdx.x == 0) panel_workgroup<RPT, NB, TG>(g, sl);
+  else if (g.b > 0) update_workgroup<RPT, NB, TG>(g);
 }
 
 __global__ void gj_gather_inverse_kernel(int n, const double* S, int lds, const int* piv, const int* pos, double* X,
@@ -433,18 +445,19 @@ __global__ void gj_scatter_rows_kernel(int w, int c0, int ncols, double* S, int 
 
 // One elimination range (all columns for a one-level elimination, one outer panel of a
 // two-level one): launches b = 0 .. nblk of gj_step_kernel.
-template <int RPT, int NB>
+template <int RPT, int NB, int TG>
 void run_gj_range(GjArgs g, hipStream_t st) {
   g.nblk = (g.npiv + NB - 1) / NB;
   g.nupd = std::min(GJ_MAXUPD, (g.cend - g.c0 + GJ_CW - 1) / GJ_CW);
-  const int lds_bytes = GJ_T * RPT * NB * (int)sizeof(double);
-  SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lds_bytes));
+  const int lds_bytes = gj_stage<RPT, NB, TG>() ? TG * RPT * NB * (int)sizeof(double) : 0;
+  if (lds_bytes)
+    SKR_HIP(hipFuncSetAttribute((const void*)gj_step_kernel<RPT, NB, TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds_bytes));
   for (int b = 0; b <= g.nblk; ++b) {
     g.b = b;
     const int grid = (b == 0) ? 1 : 1 + g.nupd;
     // only launches with a previous panel stage it; the update workgroups need no LDS
-    hipLaunchKernelGGL((gj_step_kernel<RPT, NB>), dim3(grid), dim3(GJ_T), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
+    hipLaunchKernelGGL((gj_step_kernel<RPT, NB, TG>), dim3(grid), dim3(TG), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
     check_launch("gj_step");
   }
 }
@@ -455,7 +468,7 @@ void run_gj_range(GjArgs g, hipStream_t st) {
 // over n x ncols doubles per few columns; the outer panels turn that traffic into GEMMs.
 constexpr int GJ2_W = 256, GJ2_MIN_N = 1025;
 
-template <int RPT, int NB>
+template <int RPT, int NB, int TG>
 void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
             hipStream_t st) {
   GjArgs g{};
@@ -478,7 +491,7 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
     g.npiv = n;
     g.cend = ncols;
     g.want_logdet = 1;
-    run_gj_range<RPT, NB>(g, st);
+    run_gj_range<RPT, NB, TG>(g, st);
     return;
   }
   static_assert(GJ2_W % NB == 0, "outer panels hold whole inner panels");
@@ -490,7 +503,7 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
     g.npiv = w;
     g.cend = c0 + w;
     g.want_logdet = (c0 + w == n);
-    run_gj_range<RPT, NB>(g, st);
+    run_gj_range<RPT, NB, TG>(g, st);
     if (ncols == w) continue;
     const int grid = std::max(1, std::min(4096, ceil_div((int64_t)w * ncols, 256)));
     hipLaunchKernelGGL(gj_gather_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, g.piv, A.p);
@@ -523,15 +536,17 @@ int gj_doubles(int n) { return n + 1; }
 void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
                   hipStream_t st) {
   SKR_REQUIRE(n >= 1 && ncols >= n && lds >= n, "Gauss-Jordan elimination: bad sizes");
-  SKR_REQUIRE(n <= 64 * GJ_T, "Gauss-Jordan elimination supports n <= 16384");
-  // RPT rows per thread and panel width NB with RPT * NB <= 64 register doubles
-  if (n <= GJ_T) run_gj<1, 32>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 2 * GJ_T) run_gj<2, 32>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 4 * GJ_T) run_gj<4, 16>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 8 * GJ_T) run_gj<8, 8>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 16 * GJ_T) run_gj<16, 4>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 32 * GJ_T) run_gj<32, 2>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else run_gj<64, 1>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  SKR_REQUIRE(n <= 16384, "Gauss-Jordan elimination supports n <= 16384");
+  // RPT rows per thread and panel width NB with RPT * NB <= 64 register doubles.  Up to
+  // order 1024 one wavefront per SIMD (256 threads); from 1025 to 8192, two (512 threads),
+  // which halves the number of panels (one launch each) for the same registers per thread.
+  if (n <= 256) run_gj<1, 32, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 512) run_gj<2, 32, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 1024) run_gj<4, 16, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 2048) run_gj<4, 16, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 4096) run_gj<8, 8, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else if (n <= 8192) run_gj<16, 4, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+  else run_gj<64, 1, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
 }
 
 void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st) {

@@ -190,6 +190,7 @@ struct Space {
   SrhtPlan srht;                   // DCT embedding: factorisation and sampled rows
   DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
   DBuf<int> sroff, srsamp;
+  DBuf<double> Z, cz, cstash, zf;  // delayed re-orthogonalisation of the sketched QR update
   // sketch of block j: two buffers by parity, so that the sketch of block j + 1 can be
   // written while block j's whitening still reads its own
   double* wbuf(int j) const { return (j & 1) ? w2.p : w.p; }
@@ -245,6 +246,7 @@ class Solver {
       SKR_REQUIRE(s_ < (int64_t(1) << 31), "s too large");
     }
     ld_ = (p.maxit + 1) * r;
+    delayed_ = sketched_ && whiten_delayed_supported(r);
     fast_ = cgs_supported(r, p.k);
     if (sorth_ && !fast_)
       throw Error(SKR_ENOTSUP, "the sketched-inner-product block step needs r <= 4 and k <= 3");
@@ -316,6 +318,11 @@ class Solver {
     for (int d = 1; d <= p_.maxit; ++d) {
       block_step(d);
       if (d % p_.p == 0 || d == p_.maxit) {
+        if (sketched_) {
+          prof_.begin(KF_WHITEN, aux2_);
+          flush_whiten(d, aux2_);
+          prof_.end();
+        }
         join_aux();
         SKR_HIP(hipMemcpyAsync(&hb[0], sp_[0].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
         SKR_HIP(hipMemcpyAsync(&hb[1], sp_[1].broken.p, sizeof(int), hipMemcpyDeviceToHost, st_));
@@ -423,7 +430,13 @@ class Solver {
     s.w2.alloc((size_t)s_ * r_);
     s.c1.alloc((size_t)ld_ * r_);
     s.c2.alloc((size_t)ld_ * r_);
-    s.wpart.alloc(whiten_part_doubles((int)s_, r_, p_.maxit * r_));
+    s.wpart.alloc(whiten_part_doubles((int)s_, delayed_ ? 2 * r_ : r_, p_.maxit * r_));
+    if (delayed_ && s.n > 0) {
+      s.Z.alloc((size_t)s_ * 2 * r_);
+      s.cz.alloc((size_t)ld_ * 2 * r_);
+      s.cstash.alloc((size_t)ld_ * r_);
+      s.zf.alloc((size_t)s_ * r_);
+    }
     s.ell.alloc((size_t)r_ * r_);
     if (sketched_ && !srht_) s.tab.alloc((size_t)s.n * p_.zeta);
     if (sorth_) {
@@ -679,13 +692,38 @@ class Solver {
                              pend ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
   }
 
+  WhitenSpace whiten_space(Space<T>& sp, int d) {
+    WhitenSpace w{sp.Q.p, sp.Tm.p, sp.wbuf(d + 1), sp.c1.p, sp.c2.p, sp.wpart.p, sp.broken.p, ld_};
+    w.Z = sp.Z.p;
+    w.cz = sp.cz.p;
+    w.cstash = sp.cstash.p;
+    w.zf = sp.zf.p;
+    return w;
+  }
+
+  // Sketched QR update with the sketch of block d + 1 in wbuf(d + 1).  Without delayed
+  // re-orthogonalisation (r > 8, or the first block) block d + 1 is appended at once.  With
+  // it, the new block is projected once against Q and left pending, and the block pending
+  // before (block d) is finished and appended in the same two sweeps over Q.
   void whiten(int d, int step, hipStream_t s) {
-    // appends block d + 1, whose sketch is in wbuf(d + 1)
-    WhitenSpace w0{sp_[0].Q.p, sp_[0].Tm.p, sp_[0].wbuf(d + 1), sp_[0].c1.p, sp_[0].c2.p, sp_[0].wpart.p,
-                   sp_[0].broken.p, ld_};
-    WhitenSpace w1{sp_[1].Q.p, sp_[1].Tm.p, sp_[1].wbuf(d + 1), sp_[1].c1.p, sp_[1].c2.p, sp_[1].wpart.p,
-                   sp_[1].broken.p, ld_};
-    launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s, lyap_ ? 1 : 2);
+    const WhitenSpace w0 = whiten_space(sp_[0], d), w1 = whiten_space(sp_[1], d);
+    const int ns = lyap_ ? 1 : 2;
+    if (!delayed_ || d == 0) {
+      launch_whiten(r_, (int)s_, d * r_, step, w0, w1, s, ns);
+    } else if (!pending_) {
+      launch_whiten_delayed(r_, (int)s_, d * r_, step, WHITEN_FIRST, w0, w1, s, ns);
+      pending_ = true;
+    } else {  // block d was pending since step d - 1
+      launch_whiten_delayed(r_, (int)s_, (d - 1) * r_, d - 1, WHITEN_APPEND, w0, w1, s, ns);
+    }
+  }
+
+  // Finish the pending block d + 1 (before a projected solve, which reads all of T).
+  void flush_whiten(int d, hipStream_t s) {
+    if (!delayed_ || !pending_) return;
+    const WhitenSpace w0 = whiten_space(sp_[0], d), w1 = whiten_space(sp_[1], d);
+    launch_whiten_delayed(r_, (int)s_, d * r_, d, WHITEN_FLUSH, w0, w1, s, lyap_ ? 1 : 2);
+    pending_ = false;
   }
 
   // Two-pass block step (r <= 4, k <= 3): pass 1 + reduce 1, pass 2 + reduce 2.
@@ -921,6 +959,8 @@ class Solver {
   // the sketched QR must describe the basis that the recovery uses
   bool resketch_ = false;
   bool srht_ = false;      // subsampled randomized DCT embedding instead of the sparse sign one
+  bool delayed_ = false;   // delayed re-orthogonalisation in the sketched QR update (r <= 8)
+  bool pending_ = false;   // ... with a block projected once and not yet appended to Q, T
   skr_params p_;
   hipStream_t st_;
   int64_t s_ = 0;

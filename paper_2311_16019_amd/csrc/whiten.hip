@@ -153,7 +153,7 @@ __device__ void inv_upper_small(const double* U, double* V, int r) {
 // Small R: every thread accumulates the full R x R outer products of its rows (independent
 // loads), then a wavefront + LDS reduction; large R: threads own (a, b) pairs.
 template <int R>
-__device__ void wg_gram(const double* w, int s, double* G, double* red) {
+__device__ void wg_gram(const double* w, int s, double* G, double* red, int ld = R) {
   constexpr int RR = R * R;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   if constexpr (R <= 4) {
@@ -163,7 +163,8 @@ __device__ void wg_gram(const double* w, int s, double* G, double* red) {
 #pragma unroll 4
     for (int i = tid; i < s; i += FT) {  // unrolled: several rows' loads in flight
       double x[R];
-      load_row<double, R>(w, i, x);
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[c] = w[(size_t)i * ld + c];
 #pragma unroll
       for (int a = 0; a < R; ++a)
 #pragma unroll
@@ -186,7 +187,7 @@ __device__ void wg_gram(const double* w, int s, double* G, double* red) {
     double acc = 0.0;
     if (tid < PH * RR) {
       const int p = tid % RR, ph = tid / RR, ra = p / R, rb = p % R;
-      for (int i = ph; i < s; i += PH) acc += w[(size_t)i * R + ra] * w[(size_t)i * R + rb];
+      for (int i = ph; i < s; i += PH) acc += w[(size_t)i * ld + ra] * w[(size_t)i * ld + rb];
     }
     red[tid] = acc;
     __syncthreads();
@@ -383,6 +384,145 @@ __global__ void __launch_bounds__(FIN_T) whiten_finish_reg_kernel(WhitenSpace a0
   }
 }
 
+// ---- delayed re-orthogonalisation: small kernels around the 2r-wide sweeps
+// mode 0: Z[:, r : 2r] <- w (the new block next to the pending one)
+// mode 1: zf <- Z[:, 0 : r] (the pending block, staged contiguously for its last pass)
+// mode 2: Z[:, 0 : r] <- w (a first-pass remainder becomes the pending block)
+__global__ void dcgs_move_kernel(WhitenSpace a0, WhitenSpace a1, int s, int r, int mode) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  const int total = s * r;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int i = e / r, c = e % r;
+    double* z = a.Z + (size_t)i * 2 * r;
+    if (mode == 0) z[r + c] = a.w[e];
+    else if (mode == 1) a.zf[e] = z[c];
+    else z[c] = a.w[e];
+  }
+}
+
+// One workgroup per space.  Z holds [P'' | w'] (s x 2R, row-major): the pending block after
+// both passes against the m columns of Q, and the new block after its first pass; cz the
+// products [a | b] of that sweep (m x 2R); cstash the pending block's first-pass
+// coefficients (m x R).  Finishes the pending block: q tau = P'' by Cholesky QR twice, q
+// appended as columns m .. m + R - 1 of Q, T(0 : m, m : m + R) = cstash + a and the diagonal
+// block tau; then projects the new block off q (e = q^T w', w' <- w' - q e) and leaves it in
+// Z[:, 0 : R] as the next pending block, with first-pass coefficients [b; e] in cstash.
+template <int R>
+__global__ void __launch_bounds__(FT) whiten_finish_delayed_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m,
+                                                                   int step) {
+  const WhitenSpace& a = blockIdx.x ? a1 : a0;
+  constexpr int RR = R * R, L = 2 * R;
+  __shared__ double red[FT];
+  __shared__ double G[RMAX * RMAX], R1[RMAX * RMAX], R1i[RMAX * RMAX], R2[RMAX * RMAX], R2i[RMAX * RMAX],
+      tau[RMAX * RMAX], E[RMAX * RMAX];
+  __shared__ int ok;
+  const int tid = threadIdx.x;
+  wg_gram<R>(a.Z, s, G, red, L);
+  if (tid == 0) {
+    ok = chol_upper_small(G, R1, R);
+    if (ok) inv_upper_small(R1, R1i, R);
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll 4
+    for (int i = tid; i < s; i += FT) {
+      double* z = a.Z + (size_t)i * L;
+      double y[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k <= c; ++k) t += z[k] * R1i[k * R + c];
+        y[c] = t;
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) z[c] = y[c];
+    }
+  }
+  __syncthreads();
+  if (ok) wg_gram<R>(a.Z, s, G, red, L);
+  if (tid == 0) {
+    if (ok) ok = chol_upper_small(G, R2, R);
+    if (ok) {
+      inv_upper_small(R2, R2i, R);
+      for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) {
+          double t = 0.0;
+          for (int k = 0; k < R; ++k) t += R2[i * R + k] * R1[k * R + j];
+          tau[i * R + j] = t;
+        }
+    } else {
+      atomicMin(a.broken, step);
+      for (int i = 0; i < RR; ++i) { tau[i] = (i % (R + 1) == 0) ? 1.0 : 0.0; R2i[i] = 0.0; }
+    }
+  }
+  __syncthreads();
+  // q = P1 R2^{-1} -> Q[:, m : m + R] and Z[:, 0 : R]; e = q^T w' accumulated on the way
+  // (the same reduction as wg_gram: per-thread products, wavefront sums, workgroup sum)
+  {
+    double acc[RR];
+#pragma unroll
+    for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+    for (int i = tid; i < s; i += FT) {
+      double* z = a.Z + (size_t)i * L;
+      double q[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k <= c; ++k) t += z[k] * R2i[k * R + c];
+        q[c] = ok ? t : 0.0;
+        a.Q[(size_t)(m + c) * s + i] = q[c];
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) z[c] = q[c];
+#pragma unroll
+      for (int x = 0; x < R; ++x)
+#pragma unroll
+        for (int y = 0; y < R; ++y) acc[x * R + y] += q[x] * z[R + y];
+    }
+    const int lane = tid % 64, wv = tid / 64;
+#pragma unroll
+    for (int p = 0; p < RR; ++p) {
+      const double v = wave_sum(acc[p]);
+      if (lane == 0) red[wv * RR + p] = v;
+    }
+    __syncthreads();
+    if (tid < RR) {
+      double t = 0.0;
+      for (int w = 0; w < FT / 64; ++w) t += red[w * RR + tid];
+      E[tid] = t;
+    }
+    __syncthreads();
+  }
+  // the new block off q: next pending block w' - q e in Z[:, 0 : R]
+  for (int i = tid; i < s; i += FT) {
+    double* z = a.Z + (size_t)i * L;
+    double v[R];
+#pragma unroll
+    for (int y = 0; y < R; ++y) {
+      double t = z[R + y];
+#pragma unroll
+      for (int x = 0; x < R; ++x) t -= z[x] * E[x * R + y];
+      v[y] = t;
+    }
+#pragma unroll
+    for (int y = 0; y < R; ++y) z[y] = v[y];
+  }
+  // T column block of the finished block; the pending block's coefficients [b; e]
+  for (int e = tid; e < m * R; e += FT) {
+    const int j = e / R, c = e % R;
+    const double* czj = a.cz + (size_t)j * L;
+    a.T[j + (size_t)(m + c) * a.ldt] = a.cstash[e] + czj[c];
+    a.cstash[e] = czj[R + c];
+  }
+  if (tid < RR) {
+    const int ra = tid / R, rb = tid % R;
+    a.T[(m + ra) + (size_t)(m + rb) * a.ldt] = (ra <= rb) ? tau[ra * R + rb] : 0.0;
+    a.cstash[(size_t)m * R + tid] = E[tid];
+  }
+}
+
 }  // namespace
 
 // partials of Q^T w: one m x r slab per chunk of QT_ROWS rows
@@ -439,6 +579,91 @@ void launch_whiten(int r, int s, int m, int step, const WhitenSpace& a, const Wh
     WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(ns), dim3(FT), 0, st, a, b, s, m, step));
   }
   check_launch("whiten_finish");
+}
+
+namespace {
+
+// One sweep pair over the m columns of Q for the R-wide row-major block a.w: the products
+// Q^T w summed into c1 (pass 0) or c2 (pass 1), then w -= Q c.
+template <int R>
+void sweep_pair(int s, int m, int pass, const WhitenSpace& a, const WhitenSpace& b, int ns, hipStream_t st) {
+  const int nchunk = ceil_div(s, QT_ROWS);
+  const int tile = (WT / 64) * qt_cols<R>();
+  hipLaunchKernelGGL((qtw_split_kernel<R>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+  check_launch("whiten_qtw");
+  hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * R, 256)), ns), dim3(256), 0, st, a, b,
+                     m, R, nchunk, pass);
+  check_launch("whiten_qtw_sum");
+  hipLaunchKernelGGL((qc_rows_kernel<R>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s, m, pass);
+  check_launch("whiten_qc");
+}
+
+void finish_block(int r, int s, int m, int step, const WhitenSpace& a, const WhitenSpace& b, int ns, hipStream_t st) {
+  if (r <= 4 && s <= FIN_RPT * FIN_T) {
+    switch (r) {
+      case 1: hipLaunchKernelGGL((whiten_finish_reg_kernel<1>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 2: hipLaunchKernelGGL((whiten_finish_reg_kernel<2>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      case 3: hipLaunchKernelGGL((whiten_finish_reg_kernel<3>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+      default: hipLaunchKernelGGL((whiten_finish_reg_kernel<4>), dim3(ns), dim3(FIN_T), 0, st, a, b, s, m, step); break;
+    }
+  } else {
+    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_kernel<RR_>), dim3(ns), dim3(FT), 0, st, a, b, s, m, step));
+  }
+  check_launch("whiten_finish");
+}
+
+}  // namespace
+
+void launch_whiten_delayed(int r, int s, int m, int step, int mode, const WhitenSpace& a, const WhitenSpace& b,
+                           hipStream_t st, int nspaces) {
+  SKR_REQUIRE(whiten_delayed_supported(r), "delayed re-orthogonalisation needs r <= 8");
+  SKR_REQUIRE(m >= r, "delayed re-orthogonalisation needs a finished first block");
+  const int ns = nspaces == 1 ? 1 : 2;
+  const int mv = std::max(1, std::min(2048, ceil_div((int64_t)s * r, 256)));
+  if (mode == WHITEN_FIRST) {
+    // w <- w - Q cstash with cstash = Q^T w, then the remainder becomes the pending block
+    WhitenSpace a2 = a, b2 = b;
+    a2.c1 = a.cstash;
+    b2.c1 = b.cstash;
+    WH_DISPATCH(r, sweep_pair<RR_>(s, m, 0, a2, b2, ns, st));
+    hipLaunchKernelGGL(dcgs_move_kernel, dim3(mv, ns), dim3(256), 0, st, a, b, s, r, 2);
+    check_launch("dcgs_move");
+  } else if (mode == WHITEN_APPEND) {
+    hipLaunchKernelGGL(dcgs_move_kernel, dim3(mv, ns), dim3(256), 0, st, a, b, s, r, 0);
+    check_launch("dcgs_move");
+    WhitenSpace a2 = a, b2 = b;  // the 2r-wide sweeps over [pending | new]
+    a2.w = a.Z;
+    b2.w = b.Z;
+    a2.c1 = a.cz;
+    b2.c1 = b.cz;
+    switch (r) {
+      case 1: sweep_pair<2>(s, m, 0, a2, b2, ns, st); break;
+      case 2: sweep_pair<4>(s, m, 0, a2, b2, ns, st); break;
+      case 3: sweep_pair<6>(s, m, 0, a2, b2, ns, st); break;
+      case 4: sweep_pair<8>(s, m, 0, a2, b2, ns, st); break;
+      case 5: sweep_pair<10>(s, m, 0, a2, b2, ns, st); break;
+      case 6: sweep_pair<12>(s, m, 0, a2, b2, ns, st); break;
+      case 7: sweep_pair<14>(s, m, 0, a2, b2, ns, st); break;
+      default: sweep_pair<16>(s, m, 0, a2, b2, ns, st); break;
+    }
+    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_delayed_kernel<RR_>), dim3(ns), dim3(FT), 0, st, a, b, s, m, step));
+    check_launch("whiten_finish_delayed");
+  } else {
+    SKR_REQUIRE(mode == WHITEN_FLUSH, "unknown whitening mode");
+    // the pending block, staged contiguously: its second pass, then the usual finish with
+    // T = cstash (first pass) + the second pass's coefficients
+    hipLaunchKernelGGL(dcgs_move_kernel, dim3(mv, ns), dim3(256), 0, st, a, b, s, r, 1);
+    check_launch("dcgs_move");
+    WhitenSpace a2 = a, b2 = b;
+    a2.w = a.zf;
+    b2.w = b.zf;
+    a2.c1 = a.cstash;
+    b2.c1 = b.cstash;
+    a2.c2 = a.cz;
+    b2.c2 = b.cz;
+    WH_DISPATCH(r, sweep_pair<RR_>(s, m, 1, a2, b2, ns, st));
+    finish_block(r, s, m, step, a2, b2, ns, st);
+  }
 }
 
 }  // namespace skr

@@ -17,9 +17,34 @@ struct WhitenSpace {
   double* part;   // partial products of Q^T w, one m x r slab per chunk of rows
   int* broken;    // breakdown marker of this space
   int ldt;
+  // Delayed re-orthogonalisation (whiten_delayed_supported): the pending block's remainder
+  // and the new block side by side (s x 2r row-major), their products with Q (m x 2r), the
+  // pending block's first-pass coefficients (m x r) and an s x r staging block.
+  double* Z = nullptr;
+  double* cz = nullptr;
+  double* cstash = nullptr;
+  double* zf = nullptr;
 };
 
 size_t whiten_part_doubles(int s, int r, int maxm);
+
+// Delayed classical Gram-Schmidt with re-orthogonalisation (the DCGS2 scheme of Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, Numer. Linear Algebra Appl. 2021, in block form): the
+// second pass of block j is taken in the same two sweeps over Q as the first pass of block
+// j + 1, so that Q is read twice per block step instead of four times.  Modes:
+//   WHITEN_FIRST   no block pending: first pass of the new block (in w) against the m
+//                  columns of Q; the remainder becomes the pending block.
+//   WHITEN_APPEND  pending block and new block: both against the m columns of Q in 2r-wide
+//                  sweeps; the pending block is finished (Cholesky QR twice), appended as
+//                  columns m .. m+r-1 of Q and of T; the new block's remainder, projected
+//                  off the appended columns too, becomes the pending block.
+//   WHITEN_FLUSH   the pending block alone is finished and appended (before a projected
+//                  solve, which needs T of every block).
+// `step` is the breakdown marker written if the finished block is rank deficient.
+enum { WHITEN_FIRST = 0, WHITEN_APPEND = 1, WHITEN_FLUSH = 2 };
+inline bool whiten_delayed_supported(int r) { return r <= 8; }
+void launch_whiten_delayed(int r, int s, int m, int step, int mode, const WhitenSpace& a, const WhitenSpace& b,
+                           hipStream_t st, int nspaces = 2);
 
 // Append the block for step d (m = d r current columns of Q).  `init` = true builds Q_1,
 // T_1 from w alone (m = 0).  Processes both spaces in every launch, or only `a` when
