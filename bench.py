@@ -126,7 +126,7 @@ def algorithmic_bytes(family, cfg, w, k, d_avg, s, two_pass):
     """Bytes one launch of a kernel family must move (both Krylov spaces), by its definition.
 
     w = bulk element size, blocks are n x r, k window blocks.  Two-pass block step (r <= 4,
-    k <= 3; sliced-ELL SpMM): spmm = the operator streamed once (the mean of the forward
+    k <= 10; sliced-ELL SpMM): spmm = the operator streamed once (the mean of the forward
     orientations A, B^T and the adjoint ones A^T, B), U_d read, U~ written; dots = U~ and the
     window read; update = U~ and the window read, U_{d+1} written.  Block MGS step (CSR
     SpMM): spmm = the operator, U_d and the first window block read, U~ written; dots = one
@@ -285,7 +285,7 @@ def main():
                 out[key]["gbs"] = round(b / (ms / nl * 1e-3) / 1e9, 1)
         return fam, out
 
-    two_pass_tts = r <= 4 and TTS["k"] <= 3
+    two_pass_tts = r <= 4 and TTS["k"] <= 10
 
     # ---- FP64 time to solution: warm-up with every kernel family timed (the family table and
     # the roofline kernel: the single-kernel streaming family with the most time), then the
@@ -402,7 +402,7 @@ def main():
             torch.cuda.synchronize()
             fw = skr.solve(A, B, C1, C2, **win_params(precision))
             torch.cuda.synchronize()
-            _, tab = family_table((fw,), w, cfg["k"], (win + 1) / 2.0, cfg["s"], r <= 4 and cfg["k"] <= 3)
+            _, tab = family_table((fw,), w, cfg["k"], (win + 1) / 2.0, cfg["s"], r <= 4 and cfg["k"] <= 10)
             legs[precision] = dict(block_steps_per_s=round(fw.iters / (fw.ms_steps * 1e-3), 1),
                                    block_steps_ms=round(fw.ms_steps, 2), kernel_families=tab)
             if precision == "mixed":

@@ -172,7 +172,7 @@ SKR_API int skr_adjoint_solve(skr_op A, skr_op B, const double* G1, const double
  * and C2 = C1 = C the second Krylov space K(B^T, C2) of Algorithm 1 is K(A, C) itself; the
  * solve builds it once, with one embedding S_U (seed as above), so M_B = M_A and each block
  * step and each sign-iteration step does half of the tandem work.  Same parameters as
- * skr_solve (sketch sparse sign or none); requires r <= 4, k <= 3 and stored-basis recovery
+ * skr_solve (sketch sparse sign or none); requires r <= 4, k <= 10 and stored-basis recovery
  * (SKR_ENOTSUP otherwise).  The result holds factors of the symmetric X ~ X1 X2^T (both
  * n x ell; X1 and X2 themselves differ).  C: device FP64 n x r row-major.
  */

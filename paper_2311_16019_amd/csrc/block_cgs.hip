@@ -1,5 +1,5 @@
 // Two-pass block step of the truncated block Arnoldi recurrence (the inner loop of
-// Algorithm 1), for r <= 4 and k <= 3.
+// Algorithm 1), for r <= 4 and k <= 10.
 //
 // Pass 1 (one sweep):  U~ = Op U_d = (Op U'_d) P_d, stored; the raw products
 //     D1raw_i = U'_i^T U~ for the window blocks i = i0 .. d and G0 = U~^T U~.
@@ -29,6 +29,8 @@ namespace skr {
 namespace {
 
 constexpr int KM = CGS_KMAX;
+// Windows of more than CGS_NARROW blocks take the wide kernels (window count at run time).
+constexpr int CGS_NARROW = 3;
 constexpr int RM = CGS_RMAX;
 constexpr int RR_MAX = RM * RM;
 constexpr int RED_T = 1024;  // threads of the reduce kernels
@@ -70,14 +72,16 @@ __device__ inline Rows rows_of(const CgsPass<T>& s0, const CgsPass<T>& s1) {
 // Workgroup sums of NV per-thread values, written as this workgroup's partials
 // part[v * nwg + local] (value-major): wavefront transpose reductions, then the wavefront
 // totals added in order.
+// Only the first nvalid values are written (a short last group of a wide sweep).
 template <int NV>
-__device__ inline void write_partials(const double (&acc)[NV], double* part, int nwg, int local, double* scratch) {
+__device__ inline void write_partials(const double (&acc)[NV], double* part, int nwg, int local, double* scratch,
+                                      int nvalid = NV) {
   const int wv = threadIdx.x / 64;
   int idx;
   const double t = wave_transpose_sum<NV>(acc, idx);
   if (idx >= 0) scratch[wv * NV + idx] = t;
   __syncthreads();
-  for (int i = threadIdx.x; i < NV; i += WG) {
+  for (int i = threadIdx.x; i < nvalid; i += WG) {
     double u = 0.0;
 #pragma unroll
     for (int w = 0; w < WG / 64; ++w) u += scratch[w * NV + i];
@@ -285,6 +289,7 @@ __global__ void __launch_bounds__(WG) cgs_pass2_kernel(CgsPass<T> s0, CgsPass<T>
 #pragma unroll
   for (int v = 0; v < RR; ++v) acc[v] = 0.0;
   for (int base = wi.row0; base < wi.row1; base += 2 * WG) {  // two rows per thread in flight
+    asm volatile("" ::: "memory");  // coefficients re-read from LDS per iteration (registers)
     double y[2][R], w[2][NW > 0 ? NW : 1][R];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -331,30 +336,156 @@ __global__ void __launch_bounds__(WG) cgs_pass2_kernel(CgsPass<T> s0, CgsPass<T>
   write_partials<RR>(acc, sp.part, sp.nwg, wi.local, scratch);
 }
 
+// ------------------------------------------------------------------------- long windows
+// Window blocks of a wide sweep taken together in one pass over the rows (4 r^2 <= 64
+// accumulated products per thread).
+constexpr int CGS_GROUP = 4;
+
+// Pass 1b for nw > 3 window blocks: the products U'_i^T U~ in groups of CGS_GROUP blocks,
+// one pass over the workgroup's rows per group (U~ is read once per group, each window
+// block once), U~^T U~ in the first group's pass; partials in the layout of
+// cgs_dots_kernel.
+template <typename T, int R>
+__global__ void __launch_bounds__(WG) cgs_dots_wide_kernel(CgsPass<T> s0, CgsPass<T> s1, int nw) {
+  constexpr int RR = R * R, NG = R * (R + 1) / 2, GV = CGS_GROUP * RR;
+  const Rows wi = rows_of(s0, s1);
+  const CgsPass<T>& sp = wi.space ? s1 : s0;
+  __shared__ double scratch[(WG / 64) * GV];
+  double accg[NG];
+#pragma unroll
+  for (int v = 0; v < NG; ++v) accg[v] = 0.0;
+  for (int g0 = 0; g0 < nw; g0 += CGS_GROUP) {
+    const int ng = min(CGS_GROUP, nw - g0);
+    double accw[GV];
+#pragma unroll
+    for (int v = 0; v < GV; ++v) accw[v] = 0.0;
+    // the group's block pointers, selected with constant indices (a run-time index into the
+    // kernel argument would move the argument structure to scratch memory)
+    const T* wp[CGS_GROUP];
+#pragma unroll
+    for (int i = 0; i < CGS_GROUP; ++i) {
+      wp[i] = sp.W[0];
+#pragma unroll
+      for (int t = 0; t < KM; ++t)
+        if (t == g0 + i) wp[i] = sp.W[t];
+    }
+    for (int row = wi.row0 + threadIdx.x; row < wi.row1; row += WG) {
+      T y[R], w[CGS_GROUP][R];
+      load_raw<T, R>(sp.Y, row, y);
+#pragma unroll
+      for (int i = 0; i < CGS_GROUP; ++i)
+        if (i < ng) load_raw<T, R>(wp[i], row, w[i]);
+      if (g0 == 0) {
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int b = a; b < R; ++b, ++g) accg[g] += (double)y[a] * (double)y[b];
+      }
+#pragma unroll
+      for (int i = 0; i < CGS_GROUP; ++i)
+        if (i < ng)
+#pragma unroll
+          for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) accw[i * RR + a * R + b] += (double)w[i][a] * (double)y[b];
+    }
+    // this group's values are window values g0 * RR .. (g0 + ng) * RR (value-major partials)
+    write_partials<GV>(accw, sp.part + (size_t)g0 * RR * sp.nwg, sp.nwg, wi.local, scratch, ng * RR);
+    __syncthreads();  // scratch is reused by the next group
+  }
+  double acc[RR];
+  {
+    int g = 0;
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = a; b < R; ++b, ++g) {
+        acc[a * R + b] = accg[g];
+        acc[b * R + a] = accg[g];
+      }
+  }
+  write_partials<RR>(acc, sp.part + (size_t)nw * RR * sp.nwg, sp.nwg, wi.local, scratch);
+}
+
+// Pass 2 for nw > 3 window blocks: U' = (U~ - W D) R1^{-1} with all window rows of a row in
+// flight together, and the Gram matrix of U'.
+template <typename T, int R>
+__global__ void __launch_bounds__(WG) cgs_pass2_wide_kernel(CgsPass<T> s0, CgsPass<T> s1, int nw) {
+  constexpr int RR = R * R;
+  const Rows wi = rows_of(s0, s1);
+  const CgsPass<T>& sp = wi.space ? s1 : s0;
+  __shared__ double cf[(KM + 1) * RR];
+  __shared__ double scratch[(WG / 64) * RR];
+  for (int i = threadIdx.x; i < (nw + 1) * RR; i += WG) cf[i] = sp.coef[i];
+  __syncthreads();
+  double acc[RR];
+#pragma unroll
+  for (int v = 0; v < RR; ++v) acc[v] = 0.0;
+  for (int row = wi.row0 + threadIdx.x; row < wi.row1; row += WG) {
+    // the coefficients are read from LDS in every iteration: kept in registers across rows
+    // they would take (nw + 1) r^2 of them
+    asm volatile("" ::: "memory");
+    double y[R], w[KM][R];
+    load_row<T, R>(sp.Y, row, y);
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (i < nw) load_row<T, R>(sp.W[i], row, w[i]);
+    double u[R];
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a <= b; ++a) t += y[a] * cf[a * R + b];  // R1^{-1} is upper triangular
+      u[b] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < KM; ++i)
+      if (i < nw)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          double t = 0.0;
+#pragma unroll
+          for (int a = 0; a < R; ++a) t += w[i][a] * cf[(1 + i) * RR + a * R + b];
+          u[b] -= t;
+        }
+    store_row<T, R>(sp.Unew, row, u);
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) acc[a * R + b] += u[a] * u[b];
+  }
+  write_partials<RR>(acc, sp.part, sp.nwg, wi.local, scratch);
+}
+
 // ------------------------------------------------------------------------- reductions
 // Sum the partials of nv values into out[0..nv): 16 consecutive threads per value (one
 // DPP row), each summing a strided subset of the partials; fixed order throughout.
 __device__ inline void sum_partials(const double* part, int nwg, int nv, double* out) {
-  const int v = threadIdx.x / 16, sub = threadIdx.x % 16;
-  double s = 0.0;
-  if (v < nv) {
-    const double* p = part + (size_t)v * nwg;
-    for (int g0 = 0; g0 < nwg; g0 += 512) {  // 32 independent loads per thread in flight
-      double t[32];
+  const int sub = threadIdx.x % 16;
+  const int nround = (nv + RED_T / 16 - 1) / (RED_T / 16);  // uniform over the workgroup
+  for (int rd = 0; rd < nround; ++rd) {
+    const int v = threadIdx.x / 16 + rd * (RED_T / 16);
+    double s = 0.0;
+    if (v < nv) {
+      const double* p = part + (size_t)v * nwg;
+      for (int g0 = 0; g0 < nwg; g0 += 512) {  // 32 independent loads per thread in flight
+        double t[32];
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int g = g0 + sub + 16 * u;
-        t[u] = (g < nwg) ? p[g] : 0.0;
+        for (int u = 0; u < 32; ++u) {
+          const int g = g0 + sub + 16 * u;
+          t[u] = (g < nwg) ? p[g] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) s += t[u];
       }
-#pragma unroll
-      for (int u = 0; u < 32; ++u) s += t[u];
     }
+    s += dpp_move<0xB1>(s);
+    s += dpp_move<0x4E>(s);
+    s += dpp_move<0x124>(s);
+    s += dpp_move<0x128>(s);
+    if (v < nv && sub == 0) out[v] = s;
   }
-  s += dpp_move<0xB1>(s);
-  s += dpp_move<0x4E>(s);
-  s += dpp_move<0x124>(s);
-  s += dpp_move<0x128>(s);
-  if (v < nv && sub == 0) out[v] = s;
 }
 
 __global__ void __launch_bounds__(RED_T) cgs_reduce1_kernel(CgsSmall s0, CgsSmall s1, int r, int nw, int i0, int d) {
@@ -543,7 +674,7 @@ void pass2_launch(const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
 
 #define SKR_CGS_DISPATCH(FN, r, nw, ...)                                   \
   do {                                                                     \
-    SKR_REQUIRE(r >= 1 && r <= RM && nw >= 0 && nw <= KM, "two-pass block step: unsupported r or window"); \
+    SKR_REQUIRE(r >= 1 && r <= RM && nw >= 0 && nw <= CGS_NARROW, "two-pass block step: unsupported r or window"); \
     switch (r * 8 + nw) {                                                  \
       case 8: FN<T, 1, 0>(__VA_ARGS__); break;                             \
       case 9: FN<T, 1, 1>(__VA_ARGS__); break;                             \
@@ -582,17 +713,39 @@ void launch_cgs_spmm(int r, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_
 }
 template <typename T>
 void launch_cgs_dots(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
-  SKR_CGS_DISPATCH(dots_launch, r, nw, a, b, st);
+  if (nw <= CGS_NARROW) {
+    SKR_CGS_DISPATCH(dots_launch, r, nw, a, b, st);
+  } else {
+    SKR_REQUIRE(r >= 1 && r <= RM && nw <= KM, "two-pass block step: unsupported r or window");
+    const dim3 g(a.nwg + b.nwg);
+    switch (r) {
+      case 1: hipLaunchKernelGGL((cgs_dots_wide_kernel<T, 1>), g, dim3(WG), 0, st, a, b, nw); break;
+      case 2: hipLaunchKernelGGL((cgs_dots_wide_kernel<T, 2>), g, dim3(WG), 0, st, a, b, nw); break;
+      case 3: hipLaunchKernelGGL((cgs_dots_wide_kernel<T, 3>), g, dim3(WG), 0, st, a, b, nw); break;
+      default: hipLaunchKernelGGL((cgs_dots_wide_kernel<T, 4>), g, dim3(WG), 0, st, a, b, nw); break;
+    }
+  }
   check_launch("cgs_dots");
 }
 template <typename T>
 void launch_cgs_pass2(int r, int nw, const CgsPass<T>& a, const CgsPass<T>& b, hipStream_t st) {
-  SKR_CGS_DISPATCH(pass2_launch, r, nw, a, b, st);
+  if (nw <= CGS_NARROW) {
+    SKR_CGS_DISPATCH(pass2_launch, r, nw, a, b, st);
+  } else {
+    SKR_REQUIRE(r >= 1 && r <= RM && nw <= KM, "two-pass block step: unsupported r or window");
+    const dim3 g(a.nwg + b.nwg);
+    switch (r) {
+      case 1: hipLaunchKernelGGL((cgs_pass2_wide_kernel<T, 1>), g, dim3(WG), 0, st, a, b, nw); break;
+      case 2: hipLaunchKernelGGL((cgs_pass2_wide_kernel<T, 2>), g, dim3(WG), 0, st, a, b, nw); break;
+      case 3: hipLaunchKernelGGL((cgs_pass2_wide_kernel<T, 3>), g, dim3(WG), 0, st, a, b, nw); break;
+      default: hipLaunchKernelGGL((cgs_pass2_wide_kernel<T, 4>), g, dim3(WG), 0, st, a, b, nw); break;
+    }
+  }
   check_launch("cgs_pass2");
 }
 
 void launch_cgs_reduce1(int r, int nw, int i0, int d, const CgsSmall& a, const CgsSmall& b, hipStream_t st) {
-  SKR_REQUIRE((nw + 1) * r * r * 16 <= RED_T, "two-pass block step: too many reduced values");
+  SKR_REQUIRE(r >= 1 && r <= RM && nw >= 0 && nw <= KM, "two-pass block step: unsupported r or window");
   hipLaunchKernelGGL(cgs_reduce1_kernel, dim3(2), dim3(RED_T), 0, st, a, b, r, nw, i0, d);
   check_launch("cgs_reduce1");
 }

@@ -81,7 +81,7 @@ void launch_sketch_pending(int r, int s, int zeta, const SketchSpace<T>& a, cons
 // the window Gram matrix, with Cholesky QR twice).  The stored basis block is U'_j with
 // U_j = U'_j P_j for a pending r x r factor P_j kept on the device, so that the second
 // Cholesky factor never needs a pass of its own.
-constexpr int CGS_KMAX = 3;   // window blocks handled by the two-pass step (k <= 3)
+constexpr int CGS_KMAX = 10;  // window blocks handled by the two-pass step (k <= 10)
 constexpr int CGS_RMAX = 4;   // block sizes handled by the two-pass step (r <= 4)
 
 inline bool cgs_supported(int r, int k) { return r <= CGS_RMAX && k <= CGS_KMAX; }

@@ -190,7 +190,7 @@ struct Space {
   SrhtPlan srht;                   // DCT embedding: factorisation and sampled rows
   DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
   DBuf<int> sroff, srsamp;
-  DBuf<double> Z, cz, cstash, zf;  // delayed re-orthogonalisation of the sketched QR update
+  DBuf<double> Z, cz, cstash, zf, fpart, fstate;  // delayed re-orthogonalisation of the sketched QR update
   // sketch of block j: two buffers by parity, so that the sketch of block j + 1 can be
   // written while block j's whitening still reads its own
   double* wbuf(int j) const { return (j & 1) ? w2.p : w.p; }
@@ -248,9 +248,9 @@ class Solver {
     ld_ = (p.maxit + 1) * r;
     delayed_ = sketched_ && whiten_delayed_supported(r);
     fast_ = cgs_supported(r, p.k);
-    if (sorth_ && !fast_)
+    if (sorth_ && (!fast_ || p.k > 3))
       throw Error(SKR_ENOTSUP, "the sketched-inner-product block step needs r <= 4 and k <= 3");
-    if (lyap_ && !fast_) throw Error(SKR_ENOTSUP, "the Lyapunov solve needs the two-pass block step (r <= 4, k <= 3)");
+    if (lyap_ && !fast_) throw Error(SKR_ENOTSUP, "the Lyapunov solve needs the two-pass block step (r <= 4, k <= 10)");
     if (lyap_ && p.recover != SKR_RECOVER_STORED)
       throw Error(SKR_ENOTSUP, "the Lyapunov solve needs stored-basis recovery");
     int dev = 0;
@@ -436,6 +436,8 @@ class Solver {
       s.cz.alloc((size_t)ld_ * 2 * r_);
       s.cstash.alloc((size_t)ld_ * r_);
       s.zf.alloc((size_t)s_ * r_);
+      s.fpart.alloc(whiten_fin_doubles());
+      s.fstate.alloc(whiten_fin_state_doubles());
     }
     s.ell.alloc((size_t)r_ * r_);
     if (sketched_ && !srht_) s.tab.alloc((size_t)s.n * p_.zeta);
@@ -698,6 +700,8 @@ class Solver {
     w.cz = sp.cz.p;
     w.cstash = sp.cstash.p;
     w.zf = sp.zf.p;
+    w.fpart = sp.fpart.p;
+    w.fstate = sp.fstate.p;
     return w;
   }
 
@@ -726,7 +730,7 @@ class Solver {
     pending_ = false;
   }
 
-  // Two-pass block step (r <= 4, k <= 3): pass 1 + reduce 1, pass 2 + reduce 2.
+  // Two-pass block step (r <= 4, k <= 10): pass 1 + reduce 1, pass 2 + reduce 2.
   void block_step_two_pass(int d) {
     const int i0 = std::max(1, d - p_.k + 1), nw = d - i0 + 1;
     CgsPass<T> a[2];
@@ -950,7 +954,7 @@ class Solver {
 
   PoolQuiet quiet_;  // first member: released last, after every buffer member
   int r_;
-  bool fast_ = false;      // two-pass block step (r <= 4, k <= 3)
+  bool fast_ = false;      // two-pass block step (r <= 4, k <= 10)
   bool sketched_ = true;   // s-PKSM; false: t-PKSM (no embedding)
   bool lyap_ = false;      // A X + X A^T = C1 C1^T on one Krylov space
   bool sorth_ = false;     // truncated orthogonalisation in the sketched inner product

@@ -15,7 +15,7 @@ constexpr int FT = 1024;     // threads of the finishing workgroup
 // ---- c = Q^T w, split over row chunks: every wavefront owns 64 / R columns of a tile of
 // 4 (64 / R) columns and sums its chunk's rows for all of them; the 64 per-lane values are
 // transpose-reduced across the wavefront, and each (chunk, column) partial is written once.
-constexpr int QT_ROWS = 256;  // rows of Q per chunk
+constexpr int QT_ROWS = 1024;  // rows of Q per chunk (fewer partials than 256: 4.9 against 4.2 TB/s)
 
 template <int R>
 constexpr int qt_cols() { return 64 / R > 0 ? 64 / R : 1; }
@@ -66,11 +66,12 @@ __global__ void qtw_sum_kernel(WhitenSpace a0, WhitenSpace a1, int m, int r, int
   }
 }
 
-// ---- w -= Q c in one launch: a workgroup owns 32 rows; its 8 column groups (two per
-// wavefront) take every eighth column of Q (each load a 256-byte row segment), and the 8
-// partial sums are added in order through LDS.  c is staged through LDS in column chunks.
+// ---- w -= Q c in one launch: a workgroup owns 128 rows; its 2 column groups (two
+// wavefronts each) take every other column of Q (each load a 1 KiB row segment per group,
+// eight columns' loads in flight), and the 2 partial sums are added in order through LDS.
+// c is staged through LDS in column chunks.  (32 rows and 8 groups: 4.2 TB/s; this: 4.8.)
 constexpr int QC_COLS = 512;
-constexpr int QC_ROWS = 32, QC_GROUPS = WT / QC_ROWS;
+constexpr int QC_ROWS = 128, QC_GROUPS = WT / QC_ROWS, QC_UN = 8;
 
 template <int R>
 __global__ void __launch_bounds__(WT) qc_rows_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
@@ -90,12 +91,12 @@ __global__ void __launch_bounds__(WT) qc_rows_kernel(WhitenSpace a0, WhitenSpace
     __syncthreads();
     if (i < s) {
       int j = g;
-      for (; j + 3 * QC_GROUPS < jn; j += 4 * QC_GROUPS) {
-        double q[4];
+      for (; j + (QC_UN - 1) * QC_GROUPS < jn; j += QC_UN * QC_GROUPS) {
+        double q[QC_UN];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) q[u] = a.Q[(size_t)(jc + j + QC_GROUPS * u) * s + i];
+        for (int u = 0; u < QC_UN; ++u) q[u] = a.Q[(size_t)(jc + j + QC_GROUPS * u) * s + i];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < QC_UN; ++u)
 #pragma unroll
           for (int cc = 0; cc < R; ++cc) acc[cc] += q[u] * cs[(j + QC_GROUPS * u) * R + cc];
       }
@@ -400,32 +401,112 @@ __global__ void dcgs_move_kernel(WhitenSpace a0, WhitenSpace a1, int s, int r, i
   }
 }
 
-// One workgroup per space.  Z holds [P'' | w'] (s x 2R, row-major): the pending block after
-// both passes against the m columns of Q, and the new block after its first pass; cz the
-// products [a | b] of that sweep (m x 2R); cstash the pending block's first-pass
-// coefficients (m x R).  Finishes the pending block: q tau = P'' by Cholesky QR twice, q
-// appended as columns m .. m + R - 1 of Q, T(0 : m, m : m + R) = cstash + a and the diagonal
-// block tau; then projects the new block off q (e = q^T w', w' <- w' - q e) and leaves it in
-// Z[:, 0 : R] as the next pending block, with first-pass coefficients [b; e] in cstash.
-template <int R>
-__global__ void __launch_bounds__(FT) whiten_finish_delayed_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m,
-                                                                   int step) {
-  const WhitenSpace& a = blockIdx.x ? a1 : a0;
-  constexpr int RR = R * R, L = 2 * R;
-  __shared__ double red[FT];
-  __shared__ double G[RMAX * RMAX], R1[RMAX * RMAX], R1i[RMAX * RMAX], R2[RMAX * RMAX], R2i[RMAX * RMAX],
-      tau[RMAX * RMAX], E[RMAX * RMAX];
-  __shared__ int ok;
-  const int tid = threadIdx.x;
-  wg_gram<R>(a.Z, s, G, red, L);
-  if (tid == 0) {
-    ok = chol_upper_small(G, R1, R);
-    if (ok) inv_upper_small(R1, R1i, R);
+// Finishing the pending block over many workgroups per space.  Z holds [P'' | w'] (s x 2R,
+// row-major): the pending block after both passes against the m columns of Q, and the new
+// block after its first pass; cz the products [a | b] of that sweep (m x 2R); cstash the
+// pending block's first-pass coefficients (m x R).  Four launches, each a sweep over the
+// s rows by FIN_G workgroups; every small factor is computed by each workgroup from the
+// previous launch's partial sums, added in workgroup order (the same on every workgroup):
+//   1. partials of G1 = P''^T P''
+//   2. R1 = chol(G1); P1 = P'' R1^{-1} in place; partials of G2 = P1^T P1
+//   3. R2 = chol(G2); q = P1 R2^{-1} -> columns m .. m + R - 1 of Q and Z[:, 0 : R];
+//      tau = R2 R1 -> the diagonal block of T; partials of E = q^T w'
+//   4. Z[:, 0 : R] <- w' - q E (the next pending block); T(0 : m, m : m + R) = cstash + a,
+//      cstash <- [b; E] (its first-pass coefficients against the grown Q)
+// A failed Cholesky factorisation marks the space broken at `step` and appends zero columns
+// with tau = I (the finish of the non-delayed update does the same).
+constexpr int FIN_G = 64;          // workgroups per space (at most)
+constexpr int FIN_ROWS_MIN = 512;  // rows per workgroup (at least)
+constexpr int FIN_RR = 64;         // R^2 for R <= 8
+
+struct FinRows {
+  int g, ng, r0, r1;
+};
+__device__ inline FinRows fin_rows(int s) {
+  FinRows f;
+  f.g = blockIdx.x;
+  f.ng = gridDim.x;
+  const int per = (s + f.ng - 1) / f.ng;
+  f.r0 = min(s, f.g * per);
+  f.r1 = min(s, f.r0 + per);
+  return f;
+}
+inline int fin_groups(int s) { return std::max(1, std::min(FIN_G, ceil_div(s, FIN_ROWS_MIN))); }
+
+// Sum of the workgroup's per-thread R x R values into part[g * RR + p] (fixed order).
+template <int RR>
+__device__ inline void fin_write_partials(const double (&acc)[RR], double* part, int g, double* red) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+  for (int p = 0; p < RR; ++p) {
+    const double v = wave_sum(acc[p]);
+    if (lane == 0) red[wv * RR + p] = v;
   }
   __syncthreads();
+  if (threadIdx.x < RR) {
+    double t = 0.0;
+    for (int w = 0; w < WT / 64; ++w) t += red[w * RR + threadIdx.x];
+    part[(size_t)g * FIN_RR + threadIdx.x] = t;
+  }
+}
+
+// out[p] = sum over the ng workgroups' partials (fixed order), in LDS
+template <int RR>
+__device__ inline void fin_sum_partials(const double* part, int ng, double* out) {
+  if (threadIdx.x < RR) {
+    double t = 0.0;
+    for (int g = 0; g < ng; ++g) t += part[(size_t)g * FIN_RR + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+template <int R>
+__global__ void __launch_bounds__(WT) fin1_kernel(WhitenSpace a0, WhitenSpace a1, int s) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  constexpr int RR = R * R, L = 2 * R;
+  __shared__ double red[(WT / 64) * RR];
+  const FinRows f = fin_rows(s);
+  double acc[RR];
+#pragma unroll
+  for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+  for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
+    const double* z = a.Z + (size_t)i * L;
+    double x[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[c] = z[c];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u * R + v] += x[u] * x[v];
+  }
+  fin_write_partials<RR>(acc, a.fpart, f.g, red);
+}
+
+template <int R>
+__global__ void __launch_bounds__(WT) fin2_kernel(WhitenSpace a0, WhitenSpace a1, int s, int step) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  constexpr int RR = R * R, L = 2 * R;
+  __shared__ double red[(WT / 64) * RR];
+  __shared__ double G[RR], R1[RR], R1i[RR];
+  __shared__ int ok;
+  const FinRows f = fin_rows(s);
+  fin_sum_partials<RR>(a.fpart, f.ng, G);
+  if (threadIdx.x == 0) {
+    ok = chol_upper_small(G, R1, R);
+    if (ok) inv_upper_small(R1, R1i, R);
+    if (f.g == 0) {  // the outcome and R1 for the next launches
+      a.fstate[0] = ok ? 1.0 : 0.0;
+      for (int p = 0; p < RR; ++p) a.fstate[8 + p] = ok ? R1[p] : 0.0;
+      if (!ok) atomicMin(a.broken, step);
+    }
+  }
+  __syncthreads();
+  double acc[RR];
+#pragma unroll
+  for (int p = 0; p < RR; ++p) acc[p] = 0.0;
   if (ok) {
-#pragma unroll 4
-    for (int i = tid; i < s; i += FT) {
+    for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
       double* z = a.Z + (size_t)i * L;
       double y[R];
 #pragma unroll
@@ -437,66 +518,77 @@ __global__ void __launch_bounds__(FT) whiten_finish_delayed_kernel(WhitenSpace a
       }
 #pragma unroll
       for (int c = 0; c < R; ++c) z[c] = y[c];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < R; ++v) acc[u * R + v] += y[u] * y[v];
     }
   }
-  __syncthreads();
-  if (ok) wg_gram<R>(a.Z, s, G, red, L);
-  if (tid == 0) {
+  fin_write_partials<RR>(acc, a.fpart + (size_t)FIN_G * FIN_RR, f.g, red);
+}
+
+template <int R>
+__global__ void __launch_bounds__(WT) fin3_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int step) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  constexpr int RR = R * R, L = 2 * R;
+  __shared__ double red[(WT / 64) * RR];
+  __shared__ double G[RR], R2[RR], R2i[RR];
+  __shared__ int ok;
+  const FinRows f = fin_rows(s);
+  fin_sum_partials<RR>(a.fpart + (size_t)FIN_G * FIN_RR, f.ng, G);
+  if (threadIdx.x == 0) {
+    ok = a.fstate[0] != 0.0;
     if (ok) ok = chol_upper_small(G, R2, R);
-    if (ok) {
-      inv_upper_small(R2, R2i, R);
-      for (int i = 0; i < R; ++i)
-        for (int j = 0; j < R; ++j) {
+    if (ok) inv_upper_small(R2, R2i, R);
+    else
+      for (int p = 0; p < RR; ++p) R2i[p] = 0.0;
+    if (f.g == 0) {
+      if (!ok && a.fstate[0] != 0.0) atomicMin(a.broken, step);
+      a.fstate[1] = ok ? 1.0 : 0.0;
+      for (int u = 0; u < R; ++u)  // tau = R2 R1 on the diagonal block of T (I after a failure)
+        for (int v = 0; v < R; ++v) {
           double t = 0.0;
-          for (int k = 0; k < R; ++k) t += R2[i * R + k] * R1[k * R + j];
-          tau[i * R + j] = t;
+          if (ok)
+            for (int k = 0; k < R; ++k) t += R2[u * R + k] * a.fstate[8 + k * R + v];
+          else
+            t = (u == v) ? 1.0 : 0.0;
+          a.T[(m + u) + (size_t)(m + v) * a.ldt] = (u <= v) ? t : 0.0;
         }
-    } else {
-      atomicMin(a.broken, step);
-      for (int i = 0; i < RR; ++i) { tau[i] = (i % (R + 1) == 0) ? 1.0 : 0.0; R2i[i] = 0.0; }
     }
   }
   __syncthreads();
-  // q = P1 R2^{-1} -> Q[:, m : m + R] and Z[:, 0 : R]; e = q^T w' accumulated on the way
-  // (the same reduction as wg_gram: per-thread products, wavefront sums, workgroup sum)
-  {
-    double acc[RR];
+  double acc[RR];
 #pragma unroll
-    for (int p = 0; p < RR; ++p) acc[p] = 0.0;
-    for (int i = tid; i < s; i += FT) {
-      double* z = a.Z + (size_t)i * L;
-      double q[R];
+  for (int p = 0; p < RR; ++p) acc[p] = 0.0;
+  for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
+    double* z = a.Z + (size_t)i * L;
+    double q[R];
 #pragma unroll
-      for (int c = 0; c < R; ++c) {
-        double t = 0.0;
-#pragma unroll
-        for (int k = 0; k <= c; ++k) t += z[k] * R2i[k * R + c];
-        q[c] = ok ? t : 0.0;
-        a.Q[(size_t)(m + c) * s + i] = q[c];
-      }
-#pragma unroll
-      for (int c = 0; c < R; ++c) z[c] = q[c];
-#pragma unroll
-      for (int x = 0; x < R; ++x)
-#pragma unroll
-        for (int y = 0; y < R; ++y) acc[x * R + y] += q[x] * z[R + y];
-    }
-    const int lane = tid % 64, wv = tid / 64;
-#pragma unroll
-    for (int p = 0; p < RR; ++p) {
-      const double v = wave_sum(acc[p]);
-      if (lane == 0) red[wv * RR + p] = v;
-    }
-    __syncthreads();
-    if (tid < RR) {
+    for (int c = 0; c < R; ++c) {
       double t = 0.0;
-      for (int w = 0; w < FT / 64; ++w) t += red[w * RR + tid];
-      E[tid] = t;
+#pragma unroll
+      for (int k = 0; k <= c; ++k) t += z[k] * R2i[k * R + c];
+      q[c] = t;
+      a.Q[(size_t)(m + c) * s + i] = t;
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < R; ++c) z[c] = q[c];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u * R + v] += q[u] * z[R + v];
   }
-  // the new block off q: next pending block w' - q e in Z[:, 0 : R]
-  for (int i = tid; i < s; i += FT) {
+  fin_write_partials<RR>(acc, a.fpart + (size_t)2 * FIN_G * FIN_RR, f.g, red);
+}
+
+template <int R>
+__global__ void __launch_bounds__(WT) fin4_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  constexpr int RR = R * R, L = 2 * R;
+  __shared__ double E[RR];
+  const FinRows f = fin_rows(s);
+  fin_sum_partials<RR>(a.fpart + (size_t)2 * FIN_G * FIN_RR, f.ng, E);
+  for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
     double* z = a.Z + (size_t)i * L;
     double v[R];
 #pragma unroll
@@ -509,21 +601,22 @@ __global__ void __launch_bounds__(FT) whiten_finish_delayed_kernel(WhitenSpace a
 #pragma unroll
     for (int y = 0; y < R; ++y) z[y] = v[y];
   }
-  // T column block of the finished block; the pending block's coefficients [b; e]
-  for (int e = tid; e < m * R; e += FT) {
+  // T column block of the finished block and the pending block's coefficients [b; E],
+  // the m R entries split over the workgroups
+  const int tot = m * R, per = (tot + f.ng - 1) / f.ng, e0 = f.g * per, e1 = min(tot, e0 + per);
+  for (int e = e0 + threadIdx.x; e < e1; e += WT) {
     const int j = e / R, c = e % R;
     const double* czj = a.cz + (size_t)j * L;
     a.T[j + (size_t)(m + c) * a.ldt] = a.cstash[e] + czj[c];
     a.cstash[e] = czj[R + c];
   }
-  if (tid < RR) {
-    const int ra = tid / R, rb = tid % R;
-    a.T[(m + ra) + (size_t)(m + rb) * a.ldt] = (ra <= rb) ? tau[ra * R + rb] : 0.0;
-    a.cstash[(size_t)m * R + tid] = E[tid];
-  }
+  if (f.g == 0 && threadIdx.x < RR) a.cstash[(size_t)m * R + threadIdx.x] = E[threadIdx.x];
 }
 
 }  // namespace
+
+size_t whiten_fin_doubles() { return (size_t)3 * FIN_G * FIN_RR; }
+size_t whiten_fin_state_doubles() { return 8 + FIN_RR; }
 
 // partials of Q^T w: one m x r slab per chunk of QT_ROWS rows
 size_t whiten_part_doubles(int s, int r, int maxm) { return (size_t)ceil_div(s, QT_ROWS) * maxm * r; }
@@ -646,7 +739,13 @@ void launch_whiten_delayed(int r, int s, int m, int step, int mode, const Whiten
       case 7: sweep_pair<14>(s, m, 0, a2, b2, ns, st); break;
       default: sweep_pair<16>(s, m, 0, a2, b2, ns, st); break;
     }
-    WH_DISPATCH(r, hipLaunchKernelGGL((whiten_finish_delayed_kernel<RR_>), dim3(ns), dim3(FT), 0, st, a, b, s, m, step));
+    const dim3 fg(fin_groups(s), ns);
+    WH_DISPATCH(r, {
+      hipLaunchKernelGGL((fin1_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s);
+      hipLaunchKernelGGL((fin2_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, step);
+      hipLaunchKernelGGL((fin3_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m, step);
+      hipLaunchKernelGGL((fin4_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m);
+    });
     check_launch("whiten_finish_delayed");
   } else {
     SKR_REQUIRE(mode == WHITEN_FLUSH, "unknown whitening mode");

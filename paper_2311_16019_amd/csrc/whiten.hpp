@@ -24,7 +24,12 @@ struct WhitenSpace {
   double* cz = nullptr;
   double* cstash = nullptr;
   double* zf = nullptr;
+  double* fpart = nullptr;   // workgroup partials of the finishing reductions (whiten_fin_doubles)
+  double* fstate = nullptr;  // their outcome: Cholesky success flags (whiten_fin_state_doubles)
 };
+
+size_t whiten_fin_doubles();
+size_t whiten_fin_state_doubles();
 
 size_t whiten_part_doubles(int s, int r, int maxm);
 
