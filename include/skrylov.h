@@ -208,6 +208,13 @@ SKR_API int skr_result_kernel_stats(skr_result res, int32_t idx, int32_t* count,
 SKR_API int skr_result_proj_stats(skr_result res, int32_t* newton_iters, int32_t* neg_a, int32_t* neg_b,
                                   double* proj_resid);
 
+/* Number of residual checks whose projected equation could not be solved (the sign
+ * iteration cannot separate the sketched projected matrices' spectra, which happens when the
+ * truncated bases have become numerically dependent).  Such a check is skipped: the solve goes
+ * on to the next one, and when the last check fails it returns SKR_NOT_CONVERGED with the
+ * factors of the last check that was solved. */
+SKR_API int skr_result_failed_checks(skr_result res, int32_t* failed);
+
 SKR_API int skr_result_destroy(skr_result res);
 
 /*

@@ -137,6 +137,7 @@ class Result:
     ms_recover: float = 0.0
     kernels: dict = field(default_factory=dict)  # family -> (launches, total ms), profile=True only
     proj: dict = field(default_factory=dict)     # last projected solve: newton_iters, neg_a, neg_b, resid
+    failed_checks: int = 0                       # checks whose projected equation could not be solved
 
 
 KERNEL_FAMILIES = ("spmm", "dots", "reduce", "update", "sketch", "whiten")  # skr_result_kernel_stats order
@@ -184,11 +185,14 @@ def _collect(h, n1, n2, stream):
             kernels[nm.value.decode()] = (nl.value, ms.value)
     ni, na, nb, pr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _lib.check(lib.skr_result_proj_stats(h, ctypes.byref(ni), ctypes.byref(na), ctypes.byref(nb), ctypes.byref(pr)))
+    fc = ctypes.c_int32()
+    _lib.check(lib.skr_result_failed_checks(h, ctypes.byref(fc)))
     return Result(X1=X1, X2=X2, iters=iters.value, ell=ell.value, rho_rel=rho.value,
                   status=_lib.STATUS_NAMES.get(st.value, str(st.value)),
                   history=[(d[i], rr[i]) for i in range(ln.value)],
                   ms_steps=t[0].value, ms_proj=t[1].value, ms_recover=t[2].value, kernels=kernels,
-                  proj=dict(newton_iters=ni.value, neg_a=na.value, neg_b=nb.value, resid=pr.value))
+                  proj=dict(newton_iters=ni.value, neg_a=na.value, neg_b=nb.value, resid=pr.value),
+                  failed_checks=fc.value)
 
 
 def _run(entry, A, B, C1, C2, stream, **params):

@@ -60,6 +60,7 @@ SIGNATURES = {
     "skr_result_timing": (_i32, [_vp, _pf64, _pf64, _pf64]),
     "skr_result_kernel_stats": (_i32, [_vp, _i32, _pi32, ctypes.POINTER(ctypes.c_char_p), _pi64, _pf64]),
     "skr_result_proj_stats": (_i32, [_vp, _pi32, _pi32, _pi32, _pf64]),
+    "skr_result_failed_checks": (_i32, [_vp, _pi32]),
     "skr_result_destroy": (_i32, [_vp]),
     "skr_true_residual": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),
     "skr_true_residual_adjoint": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _pf64]),

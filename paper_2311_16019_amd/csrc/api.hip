@@ -331,6 +331,14 @@ int skr_result_proj_stats(skr_result res, int32_t* newton_iters, int32_t* neg_a,
   });
 }
 
+int skr_result_failed_checks(skr_result res, int32_t* failed) {
+  return guarded([&] {
+    SKR_REQUIRE(res && failed, "null argument");
+    *failed = res->failed_checks;
+    return SKR_OK;
+  });
+}
+
 int skr_result_destroy(skr_result res) {
   delete res;
   return SKR_OK;

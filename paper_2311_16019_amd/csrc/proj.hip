@@ -642,6 +642,13 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
   dense::gemm(false, false, m, m, q, 1.0, Zr, m, Lt, q, 0.0, G, m, st_);
 }
 
+void ProjSolver::quiesce() {
+  (void)hipStreamSynchronize(st_);
+  if (aux_) (void)hipStreamSynchronize(aux_);
+  for (auto s : dst_)
+    if (s) (void)hipStreamSynchronize(s);
+}
+
 double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const double* F11, ProjStats* stats) {
   const int m = d * r_;
   SKR_REQUIRE(m <= mmax_, "projected size exceeds the allocation");

@@ -51,6 +51,8 @@ class ProjSolver {
   const double* Y2() const { return y2_.p; }
   int m() const { return m_; }
   const double* Y() const { return c_.p; }
+  // Wait for every stream of the solver (after a failed solve, before its buffers are reused).
+  void quiesce();
 
  private:
   void form(int d, const ProjSpace& sp, double* Mbar, hipStream_t st);

@@ -313,7 +313,7 @@ class Solver {
     ProjSolver proj(r_, p_.maxit * r_, st_);
     proj.use_truncated_estimate(!sketched_);
     proj.use_lyapunov(lyap_);
-    int status = SKR_NOT_CONVERGED, dfinal = 0;
+    int status = SKR_NOT_CONVERGED, dfinal = 0, dgood = 0;  // dgood: last check whose projected solve succeeded
     double rho_rel = 0.0;
     for (int d = 1; d <= p_.maxit; ++d) {
       block_step(d);
@@ -334,24 +334,53 @@ class Solver {
         res->ms_steps += ms;
         prof_.resolve(res.get());
         const int db = std::min(hb[0], hb[1]);
-        const int dc = std::min(d, db);
+        int dc = std::min(d, db);
         const bool broke = db <= d;
         SKR_REQUIRE(dc >= 1, "breakdown in the first block step");
         SKR_HIP(hipEventRecord(e0, st_));
-        ProjSpace pu{sp_[0].H.p, sp_[0].Tm.p, ld_, hb[0] == dc};
-        ProjSpace pv = lyap_ ? pu : ProjSpace{sp_[1].H.p, sp_[1].Tm.p, ld_, hb[1] == dc};
-        const double rho = proj.solve(dc, pu, pv, F11_.p, &res->last_stats);
+        auto pspaces = [&](int dd) {
+          ProjSpace pu{sp_[0].H.p, sp_[0].Tm.p, ld_, hb[0] == dd};
+          ProjSpace pv = lyap_ ? pu : ProjSpace{sp_[1].H.p, sp_[1].Tm.p, ld_, hb[1] == dd};
+          return std::make_pair(pu, pv);
+        };
+        const auto [pu, pv] = pspaces(dc);
+        const bool last_check = broke || d == p_.maxit;
+        double rho = 0.0;
+        bool solved = true;
+        try {
+          rho = proj.solve(dc, pu, pv, F11_.p, &res->last_stats);
+        } catch (const Error& e) {
+          // The projected equation could not be solved at this check (its sketched matrices
+          // have eigenvalue pairs the sign iteration cannot separate, which happens when the
+          // truncated bases are numerically dependent).  Go on to the next check; at the
+          // last one, return the factors of the last check that was solved.
+          if (e.code != SKR_EPROJ || (last_check && dgood == 0)) throw;
+          proj.quiesce();
+          solved = false;
+          ++res->failed_checks;
+        }
+        if (!solved && last_check) {
+          const auto [gu, gv] = pspaces(dgood);
+          rho = proj.solve(dgood, gu, gv, F11_.p, &res->last_stats);
+          dc = dgood;
+        }
         SKR_HIP(hipEventRecord(e1, st_));
         SKR_HIP(hipEventSynchronize(e1));
         SKR_HIP(hipEventElapsedTime(&ms, e0, e1));
         res->ms_proj += ms;
-        rho_rel = rho / rhs;
-        res->hist_d.push_back(dc);
-        res->hist_rho.push_back(rho_rel);
-        dfinal = dc;
         SKR_HIP(hipEventRecord(e0, st_));
+        if (solved || last_check) {
+          rho_rel = rho / rhs;
+          if (solved) {
+            res->hist_d.push_back(dc);
+            res->hist_rho.push_back(rho_rel);
+            dgood = dc;
+          }
+          dfinal = dc;
+        }
+        if (!solved && last_check) break;  // NOT_CONVERGED with the last solved check
         if (broke) { status = SKR_BREAKDOWN; break; }
-        if (rho_rel <= p_.tol) { status = SKR_OK; break; }
+        if (solved && rho_rel <= p_.tol) { status = SKR_OK; break; }
       }
     }
     // factors and recovery

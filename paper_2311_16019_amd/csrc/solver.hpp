@@ -28,6 +28,7 @@ struct skr_result_s {
   skr::DBuf<double> X1, X2;  // row-major n x ell
   double ms_steps = 0.0, ms_proj = 0.0, ms_recover = 0.0;
   skr::ProjStats last_stats;
+  int32_t failed_checks = 0;  // checks whose projected equation could not be solved (skipped)
 };
 
 namespace skr {

@@ -35,3 +35,40 @@ def test_full_size_lognormal_fixed_d():
     assert g.iters == o.d == prm["maxit"]
     assert product_distance(g, o) <= TOL["mixed"][0]
     assert history_ratio(g, o) <= TOL["mixed"][1]
+
+
+@pytest.mark.timeout(1500)
+def test_benchmark_configuration_forward_adjoint_gradients():
+    """The benchmark's launch configuration at full size: the n = 1e6 convection-diffusion
+    pair with r = 4, k = 10 and s = 30000, forward and adjoint solves (P1, P2 n x 4) in both
+    precisions against the oracle at a fixed d = 100 (the oracle's projected solves beyond
+    this size take minutes), and the gradients of tr(P1^T X P2) against the oracle's factors."""
+    import numpy as np
+
+    import paper_2311_16019_amd as skr
+    from gpu_helpers import gpu_ops, to_dev
+    from oracle.spksm import spksm as oracle_spksm
+    cfg = make_config("convdiff2d_1000")
+    prm = dict(k=10, maxit=100, p=100, s=30000, tol=0.0, seed=cfg["sketch_seed"])
+    print("benchmark configuration: oracle forward", flush=True)
+    of = oracle_solve(cfg, **prm)
+    print("benchmark configuration: oracle adjoint", flush=True)
+    oa = oracle_spksm(cfg["A"].transpose(), cfg["B"].transpose(), cfg["P1"], cfg["P2"], **prm)
+    A, B = gpu_ops(cfg)
+    C1, C2, P1, P2 = (to_dev(cfg[k]) for k in ("C1", "C2", "P1", "P2"))
+    # the oracle's gradients from its factors: dC1 = L1 (L2^T C2), dC2 = L2 (L1^T C1)
+    ref = {"dC1": oa.X1 @ (oa.X2.T @ cfg["C2"]), "dC2": oa.X2 @ (oa.X1.T @ cfg["C1"]),
+           "dP1": of.X1 @ (of.X2.T @ cfg["P2"]), "dP2": of.X2 @ (of.X1.T @ cfg["P1"])}
+    for precision in ("fp64", "mixed"):
+        print(f"benchmark configuration: GPU {precision}", flush=True)
+        tol_x, tol_h = TOL[precision]
+        f = skr.solve(A, B, C1, C2, precision=precision, **prm)
+        a = skr.adjoint_solve(A, B, P1, P2, precision=precision, **prm)
+        assert f.iters == a.iters == of.d == oa.d == prm["maxit"]
+        assert product_distance(f, of) <= tol_x
+        assert product_distance(a, oa) <= tol_x
+        assert history_ratio(f, of) <= tol_h and history_ratio(a, oa) <= tol_h
+        g = skr.pairing_grads(f.X1, f.X2, C1, C2, P1, P2, L1=a.X1, L2=a.X2)
+        for key, rv in ref.items():
+            err = np.linalg.norm(g[key].cpu().numpy() - rv) / np.linalg.norm(rv)
+            assert err <= tol_x, (precision, key, err)

@@ -76,3 +76,56 @@ def test_full_orthogonalisation_equals_full_arnoldi(name, m, r):
     assert g.iters == d
     dist = rel_distance(g.X1.cpu().numpy(), g.X2.cpu().numpy(), X1, X2)
     assert dist <= 1e-6, dist
+
+
+# The paper's stopping steps with p = 20 (Sec. 6, Table 2 for Ex. 6.1 at n = 90 000, Table 5
+# for Ex. 6.3): soft pins.  The embedding (the subsampled randomized DCT, s = 1600 and 500)
+# is the paper's kind but not its random draws, so the steps agree to within a few checks.
+@pytest.mark.parametrize("nu,r,d_paper", [(0.1, 1, 480), (0.01, 3, 500), (0.001, 3, 760)])
+def test_ex61_table2_stopping_steps(nu, r, d_paper):
+    import paper_2311_16019_amd as skr
+    from gpu_helpers import to_dev
+    cfg = make_config("ex61_convdiff2d_300", nu=nu, r=r)
+    prm = dict(k=10, maxit=1000, p=20, s=max(1600, 1001 * r), tol=1e-6, seed=cfg["sketch_seed"], sketch="srht")
+    print(f"ex61 table 2: nu={nu} r={r}", flush=True)
+    g, (A, B) = gpu_solve(cfg, **prm)
+    print(f"  d={g.iters} (paper {d_paper}) rank={g.ell} failed checks={g.failed_checks}", flush=True)
+    assert g.status == "converged"
+    assert abs(g.iters - d_paper) <= 0.15 * d_paper
+    tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    assert tr <= 5 * prm["tol"], tr
+
+
+@pytest.mark.parametrize("m,d_paper", [(50, 140), (100, 220)])
+def test_ex63_table5_stopping_steps(m, d_paper):
+    import paper_2311_16019_amd as skr
+    from gpu_helpers import to_dev
+    cfg = make_config("ex63_convdiff3d_100", m=m)
+    prm = dict(k=3, maxit=300, p=20, s=500, tol=1e-6, seed=cfg["sketch_seed"], sketch="srht")
+    print(f"ex63 table 5: n={m ** 3}", flush=True)
+    g, (A, B) = gpu_solve(cfg, **prm)
+    print(f"  d={g.iters} (paper {d_paper}) rank={g.ell}", flush=True)
+    assert g.status == "converged"
+    assert abs(g.iters - d_paper) <= 0.3 * d_paper
+    tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    assert tr <= 5 * prm["tol"], tr
+
+
+def test_ex61_dependent_basis_falls_back_to_last_solved_check():
+    """nu = 0.001, r = 1: the V space's truncated basis becomes numerically dependent near
+    d = 320 (the condition number of its sketched triangular factor T passes 1e14 there in the
+    oracle), and the sketched projected matrices of later checks have eigenvalue pairs the
+    sign iteration cannot separate.  Those checks are skipped; at maxit the solve returns the
+    factors of the last check that was solved, with status 'maxit', and those factors are
+    consistent: their true residual is that check's estimate up to the embedding distortion."""
+    import paper_2311_16019_amd as skr
+    from gpu_helpers import to_dev
+    cfg = make_config("ex61_convdiff2d_300", nu=0.001, r=1)
+    prm = dict(k=10, maxit=400, p=20, s=1600, tol=1e-6, seed=cfg["sketch_seed"], sketch="srht")
+    g, (A, B) = gpu_solve(cfg, **prm)
+    print(f"  d={g.iters} status={g.status} failed checks={g.failed_checks} rho={g.rho_rel:.3e}", flush=True)
+    assert g.status in ("maxit", "converged")
+    if g.failed_checks:
+        assert g.status == "maxit" and g.iters < prm["maxit"] and g.iters == g.history[-1][0]
+    tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    assert 0.2 * g.rho_rel <= tr <= 5 * g.rho_rel, (tr, g.rho_rel)

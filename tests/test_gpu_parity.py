@@ -223,3 +223,16 @@ def test_large_projected_size(precision):
     tol_x, tol_h = TOL[precision]
     assert product_distance(g, o) <= tol_x
     assert history_ratio(g, o) <= tol_h
+
+
+def test_converged_mixed_run_true_residual():
+    """A mixed-precision solve that stops on its residual estimate (the convection-diffusion
+    pair at n = 1e4, r = 4, k = 10) has a true relative residual within a small factor of the
+    tolerance: the estimate does not hide a floor of the FP32 bulk at this tolerance."""
+    import paper_2311_16019_amd as skr
+    cfg = make_config("convdiff2d_1000", m=100)
+    prm = dict(k=10, maxit=400, p=20, s=6400, tol=1e-6, seed=cfg["sketch_seed"], precision="mixed")
+    g, (A, B) = gpu_solve(cfg, **prm)
+    assert g.status == "converged", g.status
+    tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
+    assert tr <= 3 * prm["tol"], tr
