@@ -115,11 +115,15 @@ __global__ void __launch_bounds__(HQ_T) house_block_kernel(int n, int q, double*
     if (tau != 0.0 && ncols > 0) {
       for (int c0 = 0; c0 < ncols; c0 += 1024) {
         const int nc = min(1024, ncols - c0);
-        for (int c = tid; c < nc; c += HQ_T) sdot[c] = 0.0;
-        __syncthreads();
-        for (int64_t e = tid; e < (int64_t)len * nc; e += HQ_T) {
-          const int c = (int)(e % nc), i = (int)(e / nc);
-          atomicAdd(&sdot[c], v[i] * Ab[(j + i) + (size_t)(j + 1 + c0 + c) * lda]);
+        // sdot[c] = v^T A(j:, j+1+c0+c): one wavefront per column, lanes over the rows
+        // (coalesced), a fixed-order wavefront sum
+        const int lane = tid % 64, wv = tid / 64;
+        for (int c = wv; c < nc; c += HQ_T / 64) {
+          const double* col = Ab + j + (size_t)(j + 1 + c0 + c) * lda;
+          double t = 0.0;
+          for (int i = lane; i < len; i += 64) t += v[i] * col[i];
+          t = wave_sum(t);
+          if (lane == 0) sdot[c] = t;
         }
         __syncthreads();
         for (int64_t e = tid; e < (int64_t)len * nc; e += HQ_T) {

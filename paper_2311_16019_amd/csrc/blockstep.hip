@@ -433,14 +433,26 @@ __global__ void build_table_kernel(uint16_t* tab, int n, int zeta, int b, uint64
 constexpr int SK_WG = 1024;
 
 // One workgroup per (chunk of rows, copy t): scatter-add signed rows into an LDS copy of
-// the t-th band of the sketch (b x rc doubles, columns [c0, c0+rc)), then write it out.
+// the t-th band of the sketch (b x rc values, columns [c0, c0+rc)), then write it out.
 // The LDS copy is column-major (acc[c * b + bucket]) so that the 64 random buckets of a
 // wavefront's atomics spread over all LDS banks rather than over the few banks that one
 // column of a row-major copy maps to.
+//
+// The band is accumulated in 64-bit fixed point (value x 2^SK_FRAC, rounded to the nearest
+// integer): integer addition is associative, so the order in which the atomics land does
+// not change the result and every run of a solve produces the same sketch bit for bit.
+// The sketched blocks have columns of about unit norm (|entries| <= 2 for the stored
+// blocks of the two-pass step, whose pending factor is near the identity), so a bucket's
+// sum over one chunk of rows stays far below the 2^(63 - SK_FRAC) = 2048 the format holds;
+// the rounding is 2^-53 absolute per contribution, below the FP64 rounding of the entries
+// of a unit-norm sketch column.
+constexpr int SK_FRAC = 52;
+
 template <typename T, int R>
 __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, SketchSpace<T> a1, int s, int zeta,
                                                         int c0, int rc) {
-  extern __shared__ double acc[];
+  extern __shared__ unsigned long long acc[];
+  constexpr double SCALE = (double)(1ull << SK_FRAC);
   const int b = s / zeta;
   const int G = zeta * (a0.nchunk + a1.nchunk);
   const int lg = xcd_logical(blockIdx.x, G);
@@ -448,7 +460,7 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
   const SketchSpace<T>& sp = sp_id ? a1 : a0;
   const int idx = sp_id ? lg - zeta * a0.nchunk : lg;
   const int t = idx % zeta, chunk = idx / zeta;
-  for (int i = threadIdx.x; i < b * rc; i += SK_WG) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < b * rc; i += SK_WG) acc[i] = 0ull;
   __syncthreads();
   const int per = (sp.n + sp.nchunk - 1) / sp.nchunk;
   const int r0 = min(sp.n, chunk * per), r1 = min(sp.n, r0 + per);
@@ -459,15 +471,27 @@ __global__ void __launch_bounds__(SK_WG) sketch_kernel(SketchSpace<T> a0, Sketch
     const double sg = (e & 0x8000u) ? -1.0 : 1.0;
     double x[R];
     load_block_row<T, R>(sp.U, row, x);
+    if (sp.fixed) {
 #pragma unroll
-    for (int c = 0; c < R; ++c)
-      if (c >= c0 && c < c0 + rc) atomicAdd(&acc[(c - c0) * b + bucket], sg * x[c]);
+      for (int c = 0; c < R; ++c)
+        if (c >= c0 && c < c0 + rc) {
+          const long long q = __double2ll_rn(sg * x[c] * SCALE);  // two's complement: wraps exactly
+          atomicAdd(&acc[(c - c0) * b + bucket], (unsigned long long)q);
+        }
+    } else {
+      double* accd = reinterpret_cast<double*>(acc);
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (c >= c0 && c < c0 + rc) atomicAdd(&accd[(c - c0) * b + bucket], sg * x[c]);
+    }
   }
   __syncthreads();
   double* out = sp.part + ((size_t)chunk * s + (size_t)t * b) * R;
+  const double* accd = reinterpret_cast<const double*>(acc);
   for (int i = threadIdx.x; i < b * rc; i += SK_WG) {
     const int bk = i / rc, c = i % rc;
-    out[(size_t)bk * R + c0 + c] = acc[c * b + bk];
+    out[(size_t)bk * R + c0 + c] =
+        sp.fixed ? (double)(long long)acc[c * b + bk] / SCALE : accd[c * b + bk];
   }
 }
 

@@ -65,6 +65,9 @@ struct SketchSpace {
   double* part;          // [nchunk][s][r] partial sums
   double* w;             // s x r output (row-major), scaled by 1/sqrt(zeta)
   int n, nchunk;
+  // 1: the block has columns of about unit norm and is accumulated in fixed point
+  // (deterministic); 0: unbounded entries (the SpMM output U~), FP64 atomics
+  int fixed = 1;
 };
 template <typename T>
 void launch_sketch(int r, int s, int zeta, const SketchSpace<T>& a, const SketchSpace<T>& b,

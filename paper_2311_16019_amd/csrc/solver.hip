@@ -659,8 +659,8 @@ class Solver {
                      srht_args(sp_[1], sp_[1].work.p, sp_[1].skt.p, nullptr, true), lyap_ ? 1 : 2, lds_limit_, st);
       return;
     }
-    SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart2.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk};
-    SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart2.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk};
+    SketchSpace<T> k0{sp_[0].work.p, sp_[0].tab.p, sp_[0].skpart2.p, sp_[0].skt.p, sp_[0].n, sp_[0].nchunk, 0};
+    SketchSpace<T> k1{sp_[1].work.p, sp_[1].tab.p, sp_[1].skpart2.p, sp_[1].skt.p, sp_[1].n, sp_[1].nchunk, 0};
     launch_sketch_pending<T>(r_, (int)s_, p_.zeta, k0, k1, nullptr, nullptr, lds_limit_, st);
   }
 
