@@ -68,7 +68,12 @@ enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in 
  *   seed      embedding seed; S_U uses seed, S_V uses splitmix64_mix(seed + 1)
  *   zeta      nonzeros per column of the sparse sign embedding (default 8)
  *   precision SKR_FP64, or SKR_MIXED (FP32 sparse products, orthogonalisation and sketch
- *             input; FP64 sketched quantities, projected solve and residual estimate)
+ *             input; FP64 sketched quantities, projected solve and residual estimate).
+ *             In SKR_MIXED, rho is the residual of the sketched problem on the FP32-stored
+ *             basis and SKR_OK means rho met tol: the true residual can exceed rho (by 2.5x
+ *             at a residual of 1e-3 on a poorly conditioned basis; by 1.3x at 1e-6 on the
+ *             n = 1e6 convection-diffusion pair with k = 10).  A caller that needs the true
+ *             residual bounded checks it with skr_true_residual.
  *   sketch    SKR_SKETCH_SPARSE_SIGN: s-PKSM (Algorithm 1) with the sparse sign embedding
  *             (zeta nonzeros per column).  SKR_SKETCH_SRHT: s-PKSM with the subsampled
  *             randomized DCT of the paper's experiments, S x = sqrt(n/s) DCT2(E x)[rows]

@@ -27,6 +27,8 @@ namespace {
 // Relative change of the sign iterates below which the inverses are approximated
 // (Newton-Schulz); scaling is off by then (it stops below 1e-2).
 constexpr double NS_SWITCH = 5e-3;
+// projected residual above which the solution is refined once (iterative refinement)
+constexpr double REFINE_AT = 1e-10;
 
 enum Scal { MU = 0, DA, NA, TA, DB, NB_, TB, DC, NC, RHO2, RHO2B, RES2, F2, YN2, AI2, BI2, A2, B2, SCAL_N };
 
@@ -77,6 +79,11 @@ __global__ void rho_kernel(int m, int r, const double* Y, const double* hh, int 
     for (int w = 0; w < (int)blockDim.x / 64; ++w) s += red[threadIdx.x][w];
     out[threadIdx.x] = s;
   }
+}
+
+__global__ void scale_copy_kernel(size_t count, double alpha, const double* src, double* dst) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = alpha * src[e];
 }
 
 // W = M_A Y + Y M_B^T - F has been formed except for "-F"; subtract F's block and reduce.
@@ -661,18 +668,33 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   form(d, v, mbar_v_.p, aux_);
   SKR_HIP(hipEventRecord(ev_aux_, aux_));
   SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
+  double* s = scal_.p;
+  std::vector<double> hs(SCAL_N);
+  int hinfo[2];
+  double pres = 0.0;
+  // Pass 0 solves M_A Y + Y M_B^T = F.  When its projected residual misses REFINE_AT and no
+  // eigenvalue needed the deflation, pass 1 refines: the same iteration on the residual
+  // R = F - (M_A Y + Y M_B^T) gives E with M_A E + E M_B^T = R, and Y <- Y + E (iterative
+  // refinement; the sign iteration's error is relative to its right-hand side, so one
+  // refinement brings an ill-conditioned projected equation to about the square of it).
+  for (int pass = 0; pass < 2; ++pass) {
   dense::copy(m, m, mbar_u_.p, ldm, a_.p, m, st_);
   dense::transpose(m, m, mbar_v_.p, ldm, b_.p, m, st_);
-  hipLaunchKernelGGL(rhs_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, r_, F11,
-                     c_.p);
-  check_launch("rhs");
-  double* s = scal_.p;
+  if (pass == 0) {
+    hipLaunchKernelGGL(rhs_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, r_, F11,
+                       c_.p);
+    check_launch("rhs");
+  } else {  // Y -> y1_ (free until the factorisation); c = R = -(M_A Y + Y M_B^T - F), left in w1_
+    if (!y1_.p) { y1_.alloc((size_t)mmax_ * mmax_); y2_.alloc((size_t)mmax_ * mmax_); }
+    dense::copy(m, m, c_.p, m, y1_.p, m, st_);
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_,
+                       (size_t)m * m, -1.0, w1_.p, c_.p);
+    check_launch("scale_copy");
+  }
   bool scale = true;
   double prev = 1e300;
   int it = 0, extra = -1;
   const int maxit = 100;
-  std::vector<double> hs(SCAL_N);
-  int hinfo[2];
   // Near convergence the inverses are replaced by the Newton-Schulz approximation
   // X^{-1} ~ X (2I - X^2), which is the Newton step with a first-order inverse: applied to
   // the whole block matrix Z = [[A, C], [0, -B]] it gives A' = A (3I - A^2)/2, the same for B,
@@ -759,7 +781,7 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   }
   const int qa = (int)std::lround((m - hs[TA]) / 2.0), qb = (int)std::lround((m - hs[TB]) / 2.0);
   if (stats) {
-    stats->newton_iters = it;
+    if (pass == 0) stats->newton_iters = it;
     stats->neg_eigs_a = qa;
     stats->neg_eigs_b = qb;
   }
@@ -773,6 +795,11 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   dense::copy(m, m, c_.p, m, w1_.p, m, st_);
   dense::set_zero(m, m, w2_.p, m, st_);
   dense::newton_combine(m, m, s + MU, w1_.p, m, w2_.p, m, c_.p, m, s + DC, s + YN2, nullptr, scratch_.p, st_);
+  if (pass == 1) {  // Y + E
+    hipLaunchKernelGGL(add_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, y1_.p,
+                       0, c_.p);
+    check_launch("add");
+  }
   // eigenvalues in the left half plane: Y = W/2 + P_A Y + Y P_B
   if (qb > 0) {  // Y P_B with A = M_A, B = M_B^T
     deflate_right(m, mbar_u_.p, ldm, mbar_v_.p, ldm, b_.p, 0, F11, 0, qb, bi_.p);
@@ -798,7 +825,9 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   check_launch("rho");
   SKR_HIP(hipMemcpyAsync(hs.data(), s, SCAL_N * sizeof(double), hipMemcpyDeviceToHost, st_));
   SKR_HIP(hipStreamSynchronize(st_));
-  const double pres = std::sqrt(hs[RES2] / hs[F2]);
+  pres = std::sqrt(hs[RES2] / hs[F2]);
+  if (pass == 1 || pres <= REFINE_AT || qa != 0 || qb != 0) break;
+  }
   if (stats) stats->proj_resid = pres;
   if (!(pres <= 1e-6))
     throw Error(SKR_EPROJ, "projected Sylvester residual " + std::to_string(pres) + " at d = " + std::to_string(d));
