@@ -34,6 +34,19 @@ void basis_gemm(int n, int r, int nb, int l, double alpha, const T* U, const dou
 // gj_inverse (A^{-1}) and gj_solution (A^{-1} B for the columns n .. ncols-1 of S).
 void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
                   hipStream_t st);
+// Several independent eliminations, each on its own stream (arguments as for gj_eliminate),
+// enqueued interleaved launch by launch so that their chains run concurrently.
+struct GjJob {
+  int n, ncols;
+  double* S;
+  int lds;
+  int* iws;
+  double* dws;
+  int* info;
+  double* logabsdet;
+  hipStream_t st;
+};
+void gj_eliminate_many(const GjJob* jobs, int count);
 void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st);
 void gj_solution(int n, int nrhs, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st);
 int gj_ints(int n);

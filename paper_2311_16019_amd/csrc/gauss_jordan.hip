@@ -19,6 +19,9 @@
 // per-column pivot search and broadcast are latency chains that more wavefronts would only
 // time-share, but the panel width is bounded by the rows each thread holds in registers.
 #include <climits>
+#include <functional>
+#include <memory>
+#include <vector>
 #include <type_traits>
 #include <cmath>
 
@@ -443,10 +446,16 @@ __global__ void gj_scatter_rows_kernel(int w, int c0, int ncols, double* S, int 
   }
 }
 
+// The launches of one elimination as a list of closures, so that several eliminations on
+// different streams can be enqueued interleaved: enqueued one after the other, the first
+// chain's dependent launches fill its queue and hold the host until most of them have run,
+// which serialises chains meant to run concurrently.
+using GjPlan = std::vector<std::function<void()>>;
+
 // One elimination range (all columns for a one-level elimination, one outer panel of a
 // two-level one): launches b = 0 .. nblk of gj_step_kernel.
 template <int RPT, int NB, int TG>
-void run_gj_range(GjArgs g, hipStream_t st) {
+void plan_gj_range(GjArgs g, hipStream_t st, GjPlan& plan) {
   g.nblk = (g.npiv + NB - 1) / NB;
   g.nupd = std::min(GJ_MAXUPD, (g.cend - g.c0 + GJ_CW - 1) / GJ_CW);
   const int lds_bytes = gj_stage<RPT, NB, TG>() ? TG * RPT * NB * (int)sizeof(double) : 0;
@@ -457,8 +466,11 @@ void run_gj_range(GjArgs g, hipStream_t st) {
     g.b = b;
     const int grid = (b == 0) ? 1 : 1 + g.nupd;
     // only launches with a previous panel stage it; the update workgroups need no LDS
-    hipLaunchKernelGGL((gj_step_kernel<RPT, NB, TG>), dim3(grid), dim3(TG), (b > 0 && b < g.nblk) ? lds_bytes : 0, st, g);
-    check_launch("gj_step");
+    const int shm = (b > 0 && b < g.nblk) ? lds_bytes : 0;
+    plan.emplace_back([g, grid, shm, st]() {
+      hipLaunchKernelGGL((gj_step_kernel<RPT, NB, TG>), dim3(grid), dim3(TG), shm, st, g);
+      check_launch("gj_step");
+    });
   }
 }
 
@@ -469,8 +481,8 @@ void run_gj_range(GjArgs g, hipStream_t st) {
 constexpr int GJ2_W = 256, GJ2_MIN_N = 1025;
 
 template <int RPT, int NB, int TG>
-void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
-            hipStream_t st) {
+void plan_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
+             hipStream_t st, GjPlan& plan, std::vector<std::unique_ptr<DBuf<double>>>& keep) {
   GjArgs g{};
   g.n = n;
   g.ncols = ncols;
@@ -483,38 +495,45 @@ void run_gj(int n, int ncols, double* S, int lds, int* iws, double* dws, int* in
   g.info = info;
   g.pivabs = dws;
   g.logabsdet = logabsdet;
-  hipLaunchKernelGGL(gj_init_kernel, dim3(std::max(1, std::min(64, ceil_div(n, 256)))), dim3(256), 0, st, n, g.used,
-                     info);
-  check_launch("gj_init");
+  plan.emplace_back([n, used = g.used, info, st]() {
+    hipLaunchKernelGGL(gj_init_kernel, dim3(std::max(1, std::min(64, ceil_div(n, 256)))), dim3(256), 0, st, n, used,
+                       info);
+    check_launch("gj_init");
+  });
   if (n < GJ2_MIN_N) {
     g.c0 = 0;
     g.npiv = n;
     g.cend = ncols;
     g.want_logdet = 1;
-    run_gj_range<RPT, NB, TG>(g, st);
+    plan_gj_range<RPT, NB, TG>(g, st, plan);
     return;
   }
   static_assert(GJ2_W % NB == 0, "outer panels hold whole inner panels");
   const int wmax = std::min(GJ2_W, n);
-  DBuf<double> A((size_t)wmax * ncols);  // pivot rows of the other columns; reused panel after panel
+  // pivot rows of the other columns; reused panel after panel
+  keep.emplace_back(new DBuf<double>((size_t)wmax * ncols));
+  double* A = keep.back()->p;
+  const int* piv = g.piv;
   for (int c0 = 0; c0 < n; c0 += GJ2_W) {
     const int w = std::min(GJ2_W, n - c0);
     g.c0 = c0;
     g.npiv = w;
     g.cend = c0 + w;
     g.want_logdet = (c0 + w == n);
-    run_gj_range<RPT, NB, TG>(g, st);
+    plan_gj_range<RPT, NB, TG>(g, st, plan);
     if (ncols == w) continue;
-    const int grid = std::max(1, std::min(4096, ceil_div((int64_t)w * ncols, 256)));
-    hipLaunchKernelGGL(gj_gather_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, g.piv, A.p);
-    check_launch("gj_gather_rows");
-    const double* K = S + (size_t)c0 * lds;
-    if (c0 > 0) gemm(false, false, n, c0, w, 1.0, K, lds, A.p, w, 1.0, S, lds, st);
-    if (c0 + w < ncols)
-      gemm(false, false, n, ncols - c0 - w, w, 1.0, K, lds, A.p + (size_t)(c0 + w) * w, w, 1.0,
-           S + (size_t)(c0 + w) * lds, lds, st);
-    hipLaunchKernelGGL(gj_scatter_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, g.piv, A.p);
-    check_launch("gj_scatter_rows");
+    plan.emplace_back([=]() {
+      const int grid = std::max(1, std::min(4096, ceil_div((int64_t)w * ncols, 256)));
+      hipLaunchKernelGGL(gj_gather_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, piv, A);
+      check_launch("gj_gather_rows");
+      const double* K = S + (size_t)c0 * lds;
+      if (c0 > 0) gemm(false, false, n, c0, w, 1.0, K, lds, A, w, 1.0, S, lds, st);
+      if (c0 + w < ncols)
+        gemm(false, false, n, ncols - c0 - w, w, 1.0, K, lds, A + (size_t)(c0 + w) * w, w, 1.0,
+             S + (size_t)(c0 + w) * lds, lds, st);
+      hipLaunchKernelGGL(gj_scatter_rows_kernel, dim3(grid), dim3(256), 0, st, w, c0, ncols, S, lds, piv, A);
+      check_launch("gj_scatter_rows");
+    });
   }
 }
 
@@ -533,20 +552,44 @@ void gj_apply(int n, const double* S, int lds, const int* iws, const double* b, 
 }
 int gj_doubles(int n) { return n + 1; }
 
-void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
-                  hipStream_t st) {
-  SKR_REQUIRE(n >= 1 && ncols >= n && lds >= n, "Gauss-Jordan elimination: bad sizes");
+namespace {
+void plan_elimination(const GjJob& j, GjPlan& plan, std::vector<std::unique_ptr<DBuf<double>>>& keep) {
+  const int n = j.n;
+  SKR_REQUIRE(n >= 1 && j.ncols >= n && j.lds >= n, "Gauss-Jordan elimination: bad sizes");
   SKR_REQUIRE(n <= 16384, "Gauss-Jordan elimination supports n <= 16384");
   // RPT rows per thread and panel width NB with RPT * NB <= 64 register doubles.  Up to
   // order 1024 one wavefront per SIMD (256 threads); from 1025 to 8192, two (512 threads),
   // which halves the number of panels (one launch each) for the same registers per thread.
-  if (n <= 256) run_gj<1, 32, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 512) run_gj<2, 32, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 1024) run_gj<4, 16, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 2048) run_gj<4, 16, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 4096) run_gj<8, 8, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else if (n <= 8192) run_gj<16, 4, 512>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
-  else run_gj<64, 1, 256>(n, ncols, S, lds, iws, dws, info, logabsdet, st);
+#define SKR_GJ_PLAN(RPT, NB, TG) \
+  plan_gj<RPT, NB, TG>(n, j.ncols, j.S, j.lds, j.iws, j.dws, j.info, j.logabsdet, j.st, plan, keep)
+  if (n <= 256) SKR_GJ_PLAN(1, 32, 256);
+  else if (n <= 512) SKR_GJ_PLAN(2, 32, 256);
+  else if (n <= 1024) SKR_GJ_PLAN(4, 16, 256);
+  else if (n <= 2048) SKR_GJ_PLAN(4, 16, 512);
+  else if (n <= 4096) SKR_GJ_PLAN(8, 8, 512);
+  else if (n <= 8192) SKR_GJ_PLAN(16, 4, 512);
+  else SKR_GJ_PLAN(64, 1, 256);
+#undef SKR_GJ_PLAN
+}
+}  // namespace
+
+void gj_eliminate_many(const GjJob* jobs, int count) {
+  std::vector<GjPlan> plans(count);
+  std::vector<std::unique_ptr<DBuf<double>>> keep;  // released (cache-ordered) after the enqueue
+  size_t len = 0;
+  for (int i = 0; i < count; ++i) {
+    plan_elimination(jobs[i], plans[i], keep);
+    len = std::max(len, plans[i].size());
+  }
+  for (size_t t = 0; t < len; ++t)
+    for (int i = 0; i < count; ++i)
+      if (t < plans[i].size()) plans[i][t]();
+}
+
+void gj_eliminate(int n, int ncols, double* S, int lds, int* iws, double* dws, int* info, double* logabsdet,
+                  hipStream_t st) {
+  const GjJob j{n, ncols, S, lds, iws, dws, info, logabsdet, st};
+  gj_eliminate_many(&j, 1);
 }
 
 void gj_inverse(int n, const double* S, int lds, const int* iws, double* X, int ldx, hipStream_t st) {

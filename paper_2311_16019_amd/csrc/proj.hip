@@ -570,6 +570,8 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
     }
     SKR_HIP(hipEventRecord(ev_main_, st_));
     for (int u = 1; u < std::min(nr, (int)DEFL_NS); ++u) SKR_HIP(hipStreamWaitEvent(ss[u], ev_main_, 0));
+    // the shifted matrices, then their eliminations enqueued interleaved over the streams
+    std::vector<dense::GjJob> jobs;
     for (int u = 0; u < nr; ++u) {
       const int nn = reps[u].real ? m : n2, j = reps[u].j;
       if (kbv_[u].n < (size_t)4 * mmax_ * mmax_) {
@@ -585,8 +587,11 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
         hipLaunchKernelGGL(build_shift_kernel, dim3(std::min(8192, ceil_div((int64_t)n2 * n2, 256))), dim3(256), 0,
                            su, m, Al, lal, Tre, Tim, q, j, kbv_[u].p);
       check_launch("build_shift");
-      dense::gj_eliminate(nn, nn, kbv_[u].p, nn, gjwv_[u].p, gjdv_[u].p, info_.p + 2 + j, nullptr, su);
+      jobs.push_back({nn, nn, kbv_[u].p, nn, gjwv_[u].p, gjdv_[u].p, info_.p + 2 + j, nullptr, su});
     }
+    // jobs on the same stream stay in their order: interleave in rounds of DEFL_NS jobs
+    for (size_t u0 = 0; u0 < jobs.size(); u0 += DEFL_NS)
+      dense::gj_eliminate_many(jobs.data() + u0, (int)std::min<size_t>(DEFL_NS, jobs.size() - u0));
     for (int u = 1; u < std::min(nr, (int)DEFL_NS); ++u) {
       SKR_HIP(hipEventRecord(dev_[u], ss[u]));
       SKR_HIP(hipStreamWaitEvent(st_, dev_[u], 0));
@@ -706,14 +711,14 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     SKR_HIP(hipStreamWaitEvent(aux_, ev_main_, 0));
     if (!schulz) {
       // A_k^{-1} on the solve's stream and B_k^{-1} on the auxiliary stream, concurrently
-      if (!lyap_) {
-        dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
-        dense::gj_eliminate(m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, nullptr, aux_);
-        dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
-      }
-      SKR_HIP(hipEventRecord(ev_aux_, aux_));
+      // (the two elimination chains enqueued interleaved)
+      if (!lyap_) dense::copy(m, m, b_.p, m, lub_.p, m, aux_);
       dense::copy(m, m, a_.p, m, lu_.p, m, st_);
-      dense::gj_eliminate(m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, nullptr, st_);
+      const dense::GjJob jobs[2] = {{m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, nullptr, st_},
+                                    {m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, nullptr, aux_}};
+      dense::gj_eliminate_many(jobs, lyap_ ? 1 : 2);
+      if (!lyap_) dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
+      SKR_HIP(hipEventRecord(ev_aux_, aux_));
       dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
       SKR_HIP(hipStreamWaitEvent(st_, ev_aux_, 0));
       if (lyap_) dense::transpose(m, m, ai_.p, m, bi_.p, m, st_);  // B_k = A_k^T

@@ -14,6 +14,7 @@
 // do not mark the device, so that concurrent solves on other host threads are not stalled
 // by a device synchronisation.  A reused stream only orders new work after the work already
 // queued on it.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -23,7 +24,11 @@
 namespace skr {
 namespace {
 
-constexpr size_t kCacheCap = size_t(64) << 30;  // cached bytes kept per device at most
+// Cached bytes kept per device at most: 60% of the device's memory, so that the two stored
+// bases of a full-length solve (60 GB each at n = 1e6, r = 4, FP64, 1876 blocks) stay cached
+// from one solve to the next instead of being freed and allocated again (a free and an
+// allocation of that size cost about 0.6 s per solve).
+constexpr size_t kCacheCapMin = size_t(64) << 30;
 
 thread_local int tl_quiet = 0;  // depth of quiet scopes on this host thread
 constexpr int kMaxDev = 64;
@@ -35,6 +40,7 @@ struct Live {
 
 struct Pool {
   std::mutex mu;
+  size_t cap[kMaxDev] = {};  // per device, set on its first release
   std::unordered_map<void*, Live> live;
   std::multimap<std::pair<int, size_t>, void*> cached;  // (device, bytes) -> block
   size_t cached_bytes[kMaxDev] = {};
@@ -118,12 +124,23 @@ void pool_free(void* p) {
   }
   const Live L = it->second;
   P.live.erase(it);
-  if (L.bytes > kCacheCap) {
+  if (P.cap[L.dev] == 0) {
+    size_t free_b = 0, total_b = 0;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(L.dev);
+    const bool ok = hipMemGetInfo(&free_b, &total_b) == hipSuccess;
+    (void)hipSetDevice(cur);
+    if (!ok) (void)hipGetLastError();
+    P.cap[L.dev] = std::max(kCacheCapMin, ok ? total_b / 10 * 6 : size_t(0));
+  }
+  const size_t cap = P.cap[L.dev];
+  if (L.bytes > cap) {
     (void)hipFree(p);
     return;
   }
   // keep the cache bounded: drop the largest cached blocks of this device first
-  while (P.cached_bytes[L.dev] + L.bytes > kCacheCap) {
+  while (P.cached_bytes[L.dev] + L.bytes > cap) {
     auto hi = P.cached.lower_bound({L.dev + 1, 0});
     if (hi == P.cached.begin()) break;
     auto last = std::prev(hi);
