@@ -121,6 +121,101 @@ __global__ void __launch_bounds__(WT) qc_rows_kernel(WhitenSpace a0, WhitenSpace
   }
 }
 
+// ---- 16-wide sweeps on the matrix cores.  With 16 columns in w (a pair of blocks next to
+// the pending pair), the two sweeps are products with an N = 16 operand: Q^T w (m x 16) and
+// Q c (s x 16), taken by v_mfma_f64_16x16x4f64 (A(i, k) from lane i + 16 k, B(k, j) from lane
+// j + 16 k, D(4 v + g, j) in register v of lane j + 16 g).  They stay bound by the reads of Q;
+// the matrix cores replace the 16 multiply-adds per element of Q (and the LDS staging of the
+// coefficients and the wavefront transpose reductions) that made the vector kernels latency-
+// and occupancy-bound at this width.
+typedef double wm_d4 __attribute__((ext_vector_type(4)));
+constexpr int QM_UN = 8;  // loads in flight per lane
+
+// c = Q^T w for one chunk of QT_ROWS rows: each wavefront owns 16 columns of Q; per pair of
+// MFMA steps lane (i, g) reads rows r + 2 g, r + 2 g + 1 of its column (16 bytes) and the
+// same rows of w.  Partials in the layout of qtw_split_kernel.
+__global__ void __launch_bounds__(WT) qtw_mfma16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+  const WhitenSpace& a = blockIdx.z ? a1 : a0;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int j0 = (blockIdx.x * (WT / 64) + wv) * 16;
+  if (j0 >= m) return;  // uniform over the wavefront; the kernel has no barrier
+  const int r0 = blockIdx.y * QT_ROWS, r1 = min(s, r0 + QT_ROWS);
+  const int col = j0 + l16;
+  const bool cok = col < m;
+  const double* qcol = a.Q + (size_t)(cok ? col : j0) * s;
+  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  int i = r0;
+  // full groups of 8 rows: rows i + 2 g and i + 2 g + 1 for lane group g; s is even, so a
+  // 16-byte load at an even row is aligned (Q's columns start at multiples of s doubles)
+  for (; i + 8 * QM_UN <= r1; i += 8 * QM_UN) {
+    double2 qa[QM_UN];
+    double zb0[QM_UN], zb1[QM_UN];
+#pragma unroll
+    for (int u = 0; u < QM_UN; ++u) {
+      const int r = i + 8 * u + 2 * g;
+      qa[u] = cok ? *reinterpret_cast<const double2*>(qcol + r) : double2{0.0, 0.0};
+      zb0[u] = a.w[(size_t)r * 16 + l16];
+      zb1[u] = a.w[(size_t)(r + 1) * 16 + l16];
+    }
+#pragma unroll
+    for (int u = 0; u < QM_UN; ++u) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].x, zb0[u], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].y, zb1[u], acc, 0, 0, 0);
+    }
+  }
+  for (; i < r1; i += 4) {  // the rest, 4 rows per step (rows beyond r1 contribute zero)
+    const int r = i + g;
+    const bool rok = r < r1;
+    const double qv = (cok && rok) ? qcol[r] : 0.0;
+    const double zv = rok ? a.w[(size_t)r * 16 + l16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, zv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = j0 + 4 * v + g;
+    if (j < m) a.part[((size_t)blockIdx.y * m + j) * 16 + l16] = acc[v];
+  }
+}
+
+// w -= Q c for 16 rows per wavefront: lane (i, g) reads row i of column j + g of Q and row
+// j + g of c (m x 16, row-major).
+__global__ void __launch_bounds__(WT) qc_mfma16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  const double* c = which ? a.c2 : a.c1;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int i0 = (blockIdx.x * (WT / 64) + wv) * 16;
+  if (i0 >= s) return;  // uniform over the wavefront; the kernel has no barrier
+  const int row = i0 + l16;
+  const bool rok = row < s;
+  const double* qrow = a.Q + (rok ? row : i0);
+  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  int j = 0;
+  for (; j + 4 * QM_UN <= m; j += 4 * QM_UN) {
+    double qa[QM_UN], cb[QM_UN];
+#pragma unroll
+    for (int u = 0; u < QM_UN; ++u) {
+      const int jj = j + 4 * u + g;
+      qa[u] = rok ? qrow[(size_t)jj * s] : 0.0;
+      cb[u] = c[(size_t)jj * 16 + l16];
+    }
+#pragma unroll
+    for (int u = 0; u < QM_UN; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u], cb[u], acc, 0, 0, 0);
+  }
+  for (; j < m; j += 4) {  // columns beyond m contribute zero
+    const int jj = j + g;
+    const double qv = (rok && jj < m) ? qrow[(size_t)jj * s] : 0.0;
+    const double cv = (jj < m) ? c[(size_t)jj * 16 + l16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, cv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = i0 + 4 * v + g;
+    if (r < s) a.w[(size_t)r * 16 + l16] -= acc[v];
+  }
+}
+
 __device__ bool chol_upper_small(const double* G, double* U, int r) {
   for (int i = 0; i < r * r; ++i) U[i] = 0.0;
   for (int j = 0; j < r; ++j) {
@@ -681,13 +776,22 @@ namespace {
 template <int R>
 void sweep_pair(int s, int m, int pass, const WhitenSpace& a, const WhitenSpace& b, int ns, hipStream_t st) {
   const int nchunk = ceil_div(s, QT_ROWS);
-  const int tile = (WT / 64) * qt_cols<R>();
-  hipLaunchKernelGGL((qtw_split_kernel<R>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+  // the matrix-core sweeps read Q in 16-byte pairs of rows: an even s keeps them aligned
+  const bool mfma = R == 16 && s % 2 == 0;
+  if (mfma) {
+    hipLaunchKernelGGL(qtw_mfma16_kernel, dim3(ceil_div(m, (WT / 64) * 16), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+  } else {
+    const int tile = (WT / 64) * qt_cols<R>();
+    hipLaunchKernelGGL((qtw_split_kernel<R>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+  }
   check_launch("whiten_qtw");
   hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * R, 256)), ns), dim3(256), 0, st, a, b,
                      m, R, nchunk, pass);
   check_launch("whiten_qtw_sum");
-  hipLaunchKernelGGL((qc_rows_kernel<R>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s, m, pass);
+  if (mfma)
+    hipLaunchKernelGGL(qc_mfma16_kernel, dim3(ceil_div(s, (WT / 64) * 16), ns), dim3(WT), 0, st, a, b, s, m, pass);
+  else
+    hipLaunchKernelGGL((qc_rows_kernel<R>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s, m, pass);
   check_launch("whiten_qc");
 }
 
@@ -710,7 +814,7 @@ void finish_block(int r, int s, int m, int step, const WhitenSpace& a, const Whi
 void launch_whiten_delayed(int r, int s, int m, int step, int mode, const WhitenSpace& a, const WhitenSpace& b,
                            hipStream_t st, int nspaces) {
   SKR_REQUIRE(whiten_delayed_supported(r), "delayed re-orthogonalisation needs r <= 8");
-  SKR_REQUIRE(m >= r, "delayed re-orthogonalisation needs a finished first block");
+  SKR_REQUIRE(m >= 1, "delayed re-orthogonalisation needs a finished first block");
   const int ns = nspaces == 1 ? 1 : 2;
   const int mv = std::max(1, std::min(2048, ceil_div((int64_t)s * r, 256)));
   if (mode == WHITEN_FIRST) {
