@@ -339,6 +339,16 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=int(rec["bytes_per_launch"]) if rec else None,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(1000.0 * ms / nl, 2), launches=nl)
 
+    # the block-step phase as a whole: every kernel family of the block step on its three
+    # streams (the main stream's sweeps, the sketch, the sketched QR update) by its
+    # algorithmic bytes at the mean d, over the timed block-step time per tandem step
+    phase_b = sum(algorithmic_bytes(f, cfg, 8, TTS["k"], d_avg, s_tts, two_pass_tts)
+                  for f in ("spmm", "dots", "update", "sketch", "whiten"))
+    phase_s = split["steps"] * 1e-3 / steps_done
+    block_step_phase = dict(bytes_per_tandem_step=int(phase_b), us_per_tandem_step=round(1e6 * phase_s, 1),
+                            achieved=round(phase_b / phase_s / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(phase_b / phase_s / 1e9 / HBM_PEAK_GBS, 4))
+
     def solve_info(res, tr):
         return dict(iters=res.iters, status=res.status, rho_rel=res.rho_rel, true_residual=tr, ell=res.ell,
                     history=[[d, float(f"{x:.3e}")] for d, x in res.history], projected=res.proj,
@@ -364,7 +374,7 @@ def main():
                                   recovery=round(split["recover"] / args.steps, 1),
                                   grads=round(1000.0 * wall["grads"] / args.steps, 2)),
                block_steps_per_s=round(steps_done / (split["steps"] * 1e-3), 1),
-               roofline=roofline, kernel_families=fam_warm_tab,
+               roofline=roofline, block_step_phase=block_step_phase, kernel_families=fam_warm_tab,
                kernel_families_from="FP64 warm-up step, every kernel family timed (the timed steps time the "
                                     "roofline kernel's family only)")
 
