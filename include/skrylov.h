@@ -97,7 +97,8 @@ enum { SKR_ORTH_EUCLIDEAN = 0,                  /* truncated Gram-Schmidt as in 
  *             (on the benchmark problem timing every family lengthens the block steps by
  *             about a fifth; timing one family costs much less)
  *   trunc_tol relative Frobenius cutoff of the low-rank factorisation of the projected
- *             solution Y (0 keeps everything)
+ *             solution Y (0 keeps everything); 1e-12 suits FP64 and 1e-8 the FP32 bulk of
+ *             SKR_MIXED (the Python binding's defaults)
  *   orth      SKR_ORTH_EUCLIDEAN: the truncated block Gram-Schmidt and the QR of the new
  *             block use the Euclidean inner product (Algorithm 1).  SKR_ORTH_SKETCHED: both
  *             use <x, y>_S = (S x)^T (S y) instead (the alternative appendix A names):

@@ -144,9 +144,11 @@ KERNEL_FAMILIES = ("spmm", "dots", "reduce", "update", "sketch", "whiten")  # sk
 
 
 def _params(k=2, maxit=200, p=20, s=0, tol=1e-6, seed=0, zeta=8, precision="fp64", recover="stored",
-            trunc_tol=1e-12, profile=False, sketch="sparse_sign", orth="euclidean"):
+            trunc_tol=None, profile=False, sketch="sparse_sign", orth="euclidean"):
     prm = _lib.Params()
     _lib.check(_lib.load().skr_params_default(ctypes.byref(prm)))
+    if trunc_tol is None:  # the factorisation's cutoff at the accuracy of the bulk arithmetic
+        trunc_tol = 1e-12 if precision == "fp64" else 1e-8
     prm.k, prm.maxit, prm.p, prm.s, prm.tol = int(k), int(maxit), int(p), int(s), float(tol)
     prm.seed, prm.zeta, prm.trunc_tol = int(seed) & (2**64 - 1), int(zeta), float(trunc_tol)
     prm.precision = {"fp64": _lib.SKR_FP64, "mixed": _lib.SKR_MIXED}[precision]
@@ -214,7 +216,8 @@ def solve(A: Operator, B: Operator, C1, C2, stream=None, **params) -> Result:
     """Solve ``A X + X B = C1 C2^T`` (Algorithm 1); returns ``X ~ X1 X2^T`` on the GPU.
 
     ``params``: k, maxit, p, s, tol, seed, zeta, precision ('fp64' | 'mixed'),
-    recover ('stored' | 'two_pass'), trunc_tol, sketch ('sparse_sign': s-PKSM, Algorithm 1;
+    recover ('stored' | 'two_pass'), trunc_tol (default 1e-12 in FP64, 1e-8 in mixed precision),
+    sketch ('sparse_sign': s-PKSM, Algorithm 1;
     'srht': s-PKSM with the subsampled randomized DCT of Sec. 6; 'none': t-PKSM, Algorithm 2,
     no embedding), orth ('euclidean' | 'sketched': truncated
     Gram-Schmidt and QR in the sketched inner product, appendix A).

@@ -236,3 +236,23 @@ def test_converged_mixed_run_true_residual():
     assert g.status == "converged", g.status
     tr = skr.true_residual(A, B, g.X1, g.X2, to_dev(cfg["C1"]), to_dev(cfg["C2"]))
     assert tr <= 3 * prm["tol"], tr
+
+
+@pytest.mark.parametrize("r", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paired_whitening_at_odd_checks(r, precision):
+    """The sketched QR update takes the blocks in pairs (2r <= 8).  With checks at odd and
+    even steps (p = 3, maxit = 11) a check can fall between the two blocks of a pair: the
+    pending pair is finished, the block waiting for its partner is appended on its own, and
+    the pairs start again after the check.  Parity with the oracle at every check."""
+    cfg = make_config("convdiff2d_1000", m=61, r=r)
+    # s: three chunks of the sweeps over Q (1024 rows each), the last one ragged
+    prm = dict(k=3, maxit=11, p=3, s=2600, seed=1012)
+    print(f"paired whitening r={r} {precision}", flush=True)
+    g, _ = gpu_solve(cfg, precision=precision, tol=0.0, **prm)
+    o = oracle_solve(cfg, tol=0.0, **prm)
+    assert g.iters == o.d == prm["maxit"]
+    assert [d for d, _ in g.history] == [3, 6, 9, 11]
+    tol_x, tol_h = TOL[precision]
+    assert product_distance(g, o) <= tol_x
+    assert history_ratio(g, o) <= tol_h
