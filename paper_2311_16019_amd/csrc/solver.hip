@@ -99,15 +99,23 @@ __global__ void zero_small_kernel(double* small, int count) {
 // W[(j-1) r : j r, col] <- P_j W[(j-1) r : j r, col] for blocks j = 1 .. d (W column-major,
 // leading dimension ldw; P_j row-major r x r at P + j r^2).
 // [a | b] -> p for two s x r row-major blocks (both spaces: blockIdx.y)
-__global__ void pack_pair_kernel(int s, int r, const double* a0, const double* b0, double* p0, const double* a1,
-                                 const double* b1, double* p1) {
-  const double* a = blockIdx.y ? a1 : a0;
-  const double* b = blockIdx.y ? b1 : b0;
-  double* p = blockIdx.y ? p1 : p0;
-  const int total = s * 2 * r;
+// the G sketches of a group (s x r row-major each) side by side -> p (s x G r), both spaces
+constexpr int GRP_MAX = 16;  // blocks per group at most (r = 1)
+struct GroupSrc {
+  const double* w[2][GRP_MAX];
+  double* p[2];
+};
+__global__ void pack_group_kernel(int s, int r, int G, GroupSrc src) {
+  const int sp = blockIdx.y, L = G * r;
+  double* p = src.p[sp];
+  const int total = s * L;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int i = e / (2 * r), c = e % (2 * r);
-    p[e] = c < r ? a[(size_t)i * r + c] : b[(size_t)i * r + c - r];
+    const int i = e / L, c = e % L, b = c / r;
+    const double* w = src.w[sp][0];
+#pragma unroll
+    for (int t = 1; t < GRP_MAX; ++t)  // constant indices: the array stays in kernel arguments
+      if (t == b) w = src.w[sp][t];
+    p[e] = w[(size_t)i * r + c % r];
   }
 }
 
@@ -204,11 +212,12 @@ struct Space {
   DBuf<double> srz, srraw;         // its stage-1 workspace and the sketch before the pending factor
   DBuf<int> sroff, srsamp;
   DBuf<double> Z, cz, cstash, zf, fpart, fstate;  // delayed re-orthogonalisation of the sketched QR update
-  // sketch of block j: four buffers (block index mod 4), so that the sketches of the next
-  // two blocks can be written while the whitening still reads the current pair's
-  double* wbuf(int j) const { return wq[j & 3].p; }
-  DBuf<double> wq[4];
-  DBuf<double> wpair;  // whitening in pairs: the two sketches side by side (s x 2r row-major)
+  // sketch of block j: 2G buffers (block index mod 2G, G blocks per whitening group), so
+  // that the sketches of the next group can be written while the current one is whitened
+  double* wbuf(int j) const { return wq[j % nwq].p; }
+  DBuf<double> wq[2 * GRP_MAX];
+  int nwq = 4;
+  DBuf<double> wgrp;  // whitening in groups: the G sketches side by side (s x G r row-major)
   T* slot(int j) const {  // 1-based basis block j
     const int idx = stored ? (j - 1) : ((j - 1) % nslots);
     return basis.p + (size_t)idx * n * rr;
@@ -262,8 +271,17 @@ class Solver {
     }
     ld_ = (p.maxit + 1) * r;
     delayed_ = sketched_ && whiten_delayed_supported(r);
-    // whitening in pairs of blocks (a 2r-wide block per pass): Q is read twice per two blocks
-    pair_ = delayed_ && !sorth_ && whiten_delayed_supported(2 * r);
+    // whitening in groups of G blocks (a G r-wide block per pass): Q is read twice per G
+    // blocks.  r = 4: four blocks, 16 columns (the 16-wide kernels need an even s); else pairs
+    // when 2r <= 8.  A wider group asks more of the Cholesky QR of the group's remainder: with
+    // r = 1 and sixteen blocks per group, a basis that has become numerically dependent (the
+    // paper's Ex. 6.1 at nu = 0.001) let a check pass whose estimate no longer matched the true
+    // residual, which pairs do not.
+    if (delayed_ && !sorth_) {
+      if (r == 4 && s_ % 2 == 0) grp_ = 4;
+      else if (whiten_delayed_supported(2 * r)) grp_ = 2;
+    }
+    nwq_ = std::max(4, 2 * grp_);
     fast_ = cgs_supported(r, p.k);
     if (sorth_ && (!fast_ || p.k > 3))
       throw Error(SKR_ENOTSUP, "the sketched-inner-product block step needs r <= 4 and k <= 3");
@@ -472,17 +490,18 @@ class Solver {
     s.broken.alloc(1);
     s.nchunk = sketch_chunks(s.n, lyap_ ? 1 : 2);
     if (!srht_) s.skpart.alloc((size_t)s.nchunk * s_ * r_);
-    for (auto& b : s.wq) b.alloc((size_t)s_ * r_);
+    s.nwq = nwq_;
+    for (int j = 0; j < nwq_; ++j) s.wq[j].alloc((size_t)s_ * r_);
     s.c1.alloc((size_t)ld_ * r_);
     s.c2.alloc((size_t)ld_ * r_);
-    const int rw = pair_ ? 2 * r_ : r_;  // width of a whitened block
+    const int rw = grp_ * r_;  // width of a whitened block
     s.wpart.alloc(whiten_part_doubles((int)s_, delayed_ ? 2 * rw : rw, p_.maxit * r_));
     if (delayed_ && s.n > 0) {
       s.Z.alloc((size_t)s_ * 2 * rw);
       s.cz.alloc((size_t)ld_ * 2 * rw);
       s.cstash.alloc((size_t)ld_ * rw);
       s.zf.alloc((size_t)s_ * rw);
-      if (pair_) s.wpair.alloc((size_t)s_ * rw);
+      if (grp_ > 1) s.wgrp.alloc((size_t)s_ * rw);
       s.fpart.alloc(whiten_fin_doubles());
       s.fstate.alloc(whiten_fin_state_doubles());
     }
@@ -741,8 +760,8 @@ class Solver {
                              pend ? sp_[1].Pall.p + off : nullptr, lds_limit_, s);
   }
 
-  WhitenSpace whiten_space(Space<T>& sp, int d, bool pair = false) {
-    WhitenSpace w{sp.Q.p, sp.Tm.p, pair ? sp.wpair.p : sp.wbuf(d + 1), sp.c1.p, sp.c2.p, sp.wpart.p, sp.broken.p, ld_};
+  WhitenSpace whiten_space(Space<T>& sp, int d, bool group = false) {
+    WhitenSpace w{sp.Q.p, sp.Tm.p, group ? sp.wgrp.p : sp.wbuf(d + 1), sp.c1.p, sp.c2.p, sp.wpart.p, sp.broken.p, ld_};
     w.Z = sp.Z.p;
     w.cz = sp.cz.p;
     w.cstash = sp.cstash.p;
@@ -755,36 +774,38 @@ class Solver {
   // Sketched QR update with the sketch of block d + 1 in wbuf(d + 1).  Without delayed
   // re-orthogonalisation (r > 8, or the first block) block d + 1 is appended at once.  With
   // it, the new block is projected once against Q and left pending, and the block pending
-  // before is finished and appended in the same two sweeps over Q.  In pairs (2r <= 8), block
-  // d + 1 waits for block d + 2, and the two sketches go through these steps as one 2r-wide
-  // block.  The host tracks the columns of Q already final (fin_cols_) and the width of the
-  // pending block (pend_w_); ev_whiten_[j & 3] is recorded after the work that read wbuf(j).
+  // before is finished and appended in the same two sweeps over Q.  In groups (grp_ > 1),
+  // blocks wait until grp_ of them are there, and their sketches go through these steps as
+  // one (grp_ r)-wide block.  The host tracks the columns of Q already final (fin_cols_), the
+  // width of the pending block (pend_w_) and the blocks waiting (held_);
+  // ev_whiten_[j mod nwq_] is recorded after the work that read wbuf(j).
   void whiten(int d, int step, hipStream_t s) {
     const int ns = lyap_ ? 1 : 2;
     if (!delayed_ || d == 0) {
       const WhitenSpace w0 = whiten_space(sp_[0], d), w1 = whiten_space(sp_[1], d);
       launch_whiten(r_, (int)s_, fin_cols_, step, w0, w1, s, ns);
       fin_cols_ += r_;
-      SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 3], s));
+      SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) % nwq_], s));
       return;
     }
-    if (pair_ && !held_) {  // block d + 1 waits for its partner
-      held_ = true;
-      return;
-    }
-    const bool pair = pair_;
-    const int w = pair ? 2 * r_ : r_;
-    if (pair) {  // [wbuf(d) | wbuf(d + 1)] -> wpair
+    const bool group = grp_ > 1;
+    if (group && ++held_ < grp_) return;  // block d + 1 waits for the rest of its group
+    const int w = grp_ * r_;
+    if (group) {  // wbuf(d + 2 - grp_) .. wbuf(d + 1) side by side -> wgrp
+      GroupSrc src{};
+      for (int q = 0; q < 2; ++q) {
+        Space<T>& sp = sp_[lyap_ ? 0 : q];
+        for (int t = 0; t < GRP_MAX; ++t) src.w[q][t] = sp.wbuf(d + 2 - grp_ + std::min(t, grp_ - 1));
+        src.p[q] = sp.wgrp.p;
+      }
       const int mv = std::max(1, std::min(2048, ceil_div((int64_t)s_ * w, 256)));
-      hipLaunchKernelGGL(pack_pair_kernel, dim3(mv, ns), dim3(256), 0, s, (int)s_, r_, sp_[0].wbuf(d),
-                         sp_[0].wbuf(d + 1), sp_[0].wpair.p, sp_[1].wbuf(d), sp_[1].wbuf(d + 1), sp_[1].wpair.p);
-      check_launch("pack_pair");
-      SKR_HIP(hipEventRecord(ev_whiten_[d & 3], s));
-      SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 3], s));
-      held_ = false;
+      hipLaunchKernelGGL(pack_group_kernel, dim3(mv, ns), dim3(256), 0, s, (int)s_, r_, grp_, src);
+      check_launch("pack_group");
+      for (int j = d + 2 - grp_; j <= d + 1; ++j) SKR_HIP(hipEventRecord(ev_whiten_[j % nwq_], s));
+      held_ = 0;
     }
-    const WhitenSpace w0 = whiten_space(sp_[0], d, pair), w1 = whiten_space(sp_[1], d, pair);
-    const int first_step = pair ? d - 1 : d;  // the step that produced the new block's first block
+    const WhitenSpace w0 = whiten_space(sp_[0], d, group), w1 = whiten_space(sp_[1], d, group);
+    const int first_step = d + 1 - grp_;  // the step that produced the new block's first block
     if (pend_w_ == 0) {
       launch_whiten_delayed(w, (int)s_, fin_cols_, first_step, WHITEN_FIRST, w0, w1, s, ns);
     } else {
@@ -793,11 +814,11 @@ class Solver {
     }
     pend_w_ = w;
     pend_step_ = first_step;
-    if (!pair) SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 3], s));  // the sweeps read wbuf(d + 1)
+    if (!group) SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) % nwq_], s));  // the sweeps read wbuf(d + 1)
   }
 
   // Finish every block up to d + 1 (before a projected solve, which reads all of T): the
-  // pending block, then a block still waiting for its partner, on its own.
+  // pending block, then the blocks still waiting for the rest of their group, one by one.
   void flush_whiten(int d, hipStream_t s) {
     if (!delayed_) return;
     const int ns = lyap_ ? 1 : 2;
@@ -807,13 +828,13 @@ class Solver {
       fin_cols_ += pend_w_;
       pend_w_ = 0;
     }
-    if (held_) {
-      const WhitenSpace w0 = whiten_space(sp_[0], d), w1 = whiten_space(sp_[1], d);
-      launch_whiten(r_, (int)s_, fin_cols_, d, w0, w1, s, ns);
+    for (int j = d + 2 - held_; j <= d + 1; ++j) {  // block j, sketched at step j - 1
+      const WhitenSpace w0 = whiten_space(sp_[0], j - 1), w1 = whiten_space(sp_[1], j - 1);
+      launch_whiten(r_, (int)s_, fin_cols_, j - 1, w0, w1, s, ns);
       fin_cols_ += r_;
-      held_ = false;
-      SKR_HIP(hipEventRecord(ev_whiten_[(d + 1) & 3], s));
+      SKR_HIP(hipEventRecord(ev_whiten_[j % nwq_], s));
     }
+    held_ = 0;
     SKR_REQUIRE(fin_cols_ == (d + 1) * r_, "sketched QR update out of step with the block steps");
   }
 
@@ -860,7 +881,7 @@ class Solver {
     prof_.end();
     // the sketch-space step writes the whitening input wbuf(d + 1), which the whitening of
     // step d - 4 read
-    SKR_HIP(hipStreamWaitEvent(st_, ev_whiten_[(d + 1) & 3], 0));
+    SKR_HIP(hipStreamWaitEvent(st_, ev_whiten_[(d + 1) % nwq_], 0));
     prof_.begin(KF_REDUCE);
     launch_sorth(r_, (int)s_, nw, i0, d, sorth_args(sp_[0], sp_[0].H.p, ld_, d + 1),
                  sorth_args(sp_[1], sp_[1].H.p, ld_, d + 1), lyap_ ? 1 : 2, st_);
@@ -890,7 +911,7 @@ class Solver {
     SKR_HIP(hipEventRecord(ev_block_, st_));
     SKR_HIP(hipStreamWaitEvent(aux_, ev_block_, 0));
     // the whitening of block d - 3 read the buffer that the sketch of block d + 1 writes
-    SKR_HIP(hipStreamWaitEvent(aux_, ev_whiten_[(d + 1) & 3], 0));
+    SKR_HIP(hipStreamWaitEvent(aux_, ev_whiten_[(d + 1) % nwq_], 0));
     prof_.begin(KF_SKETCH, aux_);
     sketch(d + 1, aux_);
     prof_.end();
@@ -1049,8 +1070,9 @@ class Solver {
   bool resketch_ = false;
   bool srht_ = false;      // subsampled randomized DCT embedding instead of the sparse sign one
   bool delayed_ = false;   // delayed re-orthogonalisation in the sketched QR update (r <= 8)
-  bool pair_ = false;      // ... on pairs of blocks (2r-wide)
-  bool held_ = false;      // a block whose sketch waits for its partner
+  int grp_ = 1;            // ... on groups of grp_ blocks (grp_ r wide)
+  int held_ = 0;           // blocks whose sketches wait for the rest of their group
+  int nwq_ = 4;            // sketch buffers per space
   int pend_w_ = 0;         // width of the block projected once and not yet appended to Q, T
   int pend_step_ = 0;      // the step that produced its first block
   int fin_cols_ = 0;       // columns of Q and T that are final
@@ -1064,7 +1086,7 @@ class Solver {
   hipStream_t aux_ = nullptr;   // sketches
   hipStream_t aux2_ = nullptr;  // sketched QR updates (whitening)
   hipEvent_t ev_block_ = nullptr, ev_sketch_ = nullptr, ev_aux_done_ = nullptr;
-  hipEvent_t ev_whiten_[4] = {nullptr, nullptr, nullptr, nullptr};  // last whitening that read wbuf(j), j mod 4
+  hipEvent_t ev_whiten_[2 * GRP_MAX] = {};  // last whitening that read wbuf(j), j mod nwq_
   DBuf<double> F11_;
   std::vector<double> rhs_block_host_;
 };

@@ -131,10 +131,13 @@ __global__ void __launch_bounds__(WT) qc_rows_kernel(WhitenSpace a0, WhitenSpace
 typedef double wm_d4 __attribute__((ext_vector_type(4)));
 constexpr int QM_UN = 8;  // loads in flight per lane
 
-// c = Q^T w for one chunk of QT_ROWS rows: each wavefront owns 16 columns of Q; per pair of
-// MFMA steps lane (i, g) reads rows r + 2 g, r + 2 g + 1 of its column (16 bytes) and the
-// same rows of w.  Partials in the layout of qtw_split_kernel.
-__global__ void __launch_bounds__(WT) qtw_mfma16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+// c = Q^T w (w with 16 NT columns, row-major) for one chunk of QT_ROWS rows: each wavefront
+// owns 16 columns of Q; per pair of MFMA steps lane (i, g) reads rows r + 2 g, r + 2 g + 1 of
+// its column (16 bytes) and the same rows of w, one 16-column tile of w per accumulator.
+// Partials in the layout of qtw_split_kernel.
+template <int NT>
+__global__ void __launch_bounds__(WT) qtw_mfma_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+  constexpr int LD = 16 * NT;
   const WhitenSpace& a = blockIdx.z ? a1 : a0;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   const int g = lane >> 4, l16 = lane & 15;
@@ -144,43 +147,57 @@ __global__ void __launch_bounds__(WT) qtw_mfma16_kernel(WhitenSpace a0, WhitenSp
   const int col = j0 + l16;
   const bool cok = col < m;
   const double* qcol = a.Q + (size_t)(cok ? col : j0) * s;
-  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  wm_d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = wm_d4{0.0, 0.0, 0.0, 0.0};
   int i = r0;
   // full groups of 8 rows: rows i + 2 g and i + 2 g + 1 for lane group g; s is even, so a
   // 16-byte load at an even row is aligned (Q's columns start at multiples of s doubles)
   for (; i + 8 * QM_UN <= r1; i += 8 * QM_UN) {
     double2 qa[QM_UN];
-    double zb0[QM_UN], zb1[QM_UN];
+    double zb0[QM_UN][NT], zb1[QM_UN][NT];
 #pragma unroll
     for (int u = 0; u < QM_UN; ++u) {
       const int r = i + 8 * u + 2 * g;
       qa[u] = cok ? *reinterpret_cast<const double2*>(qcol + r) : double2{0.0, 0.0};
-      zb0[u] = a.w[(size_t)r * 16 + l16];
-      zb1[u] = a.w[(size_t)(r + 1) * 16 + l16];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        zb0[u][t] = a.w[(size_t)r * LD + 16 * t + l16];
+        zb1[u][t] = a.w[(size_t)(r + 1) * LD + 16 * t + l16];
+      }
     }
 #pragma unroll
-    for (int u = 0; u < QM_UN; ++u) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].x, zb0[u], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].y, zb1[u], acc, 0, 0, 0);
-    }
+    for (int u = 0; u < QM_UN; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].x, zb0[u][t], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u].y, zb1[u][t], acc[t], 0, 0, 0);
+      }
   }
   for (; i < r1; i += 4) {  // the rest, 4 rows per step (rows beyond r1 contribute zero)
     const int r = i + g;
     const bool rok = r < r1;
     const double qv = (cok && rok) ? qcol[r] : 0.0;
-    const double zv = rok ? a.w[(size_t)r * 16 + l16] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, zv, acc, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double zv = rok ? a.w[(size_t)r * LD + 16 * t + l16] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, zv, acc[t], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int j = j0 + 4 * v + g;
-    if (j < m) a.part[((size_t)blockIdx.y * m + j) * 16 + l16] = acc[v];
+    if (j < m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) a.part[((size_t)blockIdx.y * m + j) * LD + 16 * t + l16] = acc[t][v];
   }
 }
 
-// w -= Q c for 16 rows per wavefront: lane (i, g) reads row i of column j + g of Q and row
-// j + g of c (m x 16, row-major).
-__global__ void __launch_bounds__(WT) qc_mfma16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
+// w -= Q c (w and c with 16 NT columns, row-major) for 16 rows per wavefront: lane (i, g)
+// reads row i of column j + g of Q and row j + g of c.
+template <int NT>
+__global__ void __launch_bounds__(WT) qc_mfma_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int which) {
+  constexpr int LD = 16 * NT;
   const WhitenSpace& a = blockIdx.y ? a1 : a0;
   const double* c = which ? a.c2 : a.c1;
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
@@ -190,29 +207,39 @@ __global__ void __launch_bounds__(WT) qc_mfma16_kernel(WhitenSpace a0, WhitenSpa
   const int row = i0 + l16;
   const bool rok = row < s;
   const double* qrow = a.Q + (rok ? row : i0);
-  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  wm_d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = wm_d4{0.0, 0.0, 0.0, 0.0};
   int j = 0;
   for (; j + 4 * QM_UN <= m; j += 4 * QM_UN) {
-    double qa[QM_UN], cb[QM_UN];
+    double qa[QM_UN], cb[QM_UN][NT];
 #pragma unroll
     for (int u = 0; u < QM_UN; ++u) {
       const int jj = j + 4 * u + g;
       qa[u] = rok ? qrow[(size_t)jj * s] : 0.0;
-      cb[u] = c[(size_t)jj * 16 + l16];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cb[u][t] = c[(size_t)jj * LD + 16 * t + l16];
     }
 #pragma unroll
-    for (int u = 0; u < QM_UN; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u], cb[u], acc, 0, 0, 0);
+    for (int u = 0; u < QM_UN; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u], cb[u][t], acc[t], 0, 0, 0);
   }
   for (; j < m; j += 4) {  // columns beyond m contribute zero
     const int jj = j + g;
     const double qv = (rok && jj < m) ? qrow[(size_t)jj * s] : 0.0;
-    const double cv = (jj < m) ? c[(size_t)jj * 16 + l16] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, cv, acc, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double cv = (jj < m) ? c[(size_t)jj * LD + 16 * t + l16] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv, cv, acc[t], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = i0 + 4 * v + g;
-    if (r < s) a.w[(size_t)r * 16 + l16] -= acc[v];
+    if (r < s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) a.w[(size_t)r * LD + 16 * t + l16] -= acc[t][v];
   }
 }
 
@@ -512,7 +539,7 @@ __global__ void dcgs_move_kernel(WhitenSpace a0, WhitenSpace a1, int s, int r, i
 // with tau = I (the finish of the non-delayed update does the same).
 constexpr int FIN_G = 64;          // workgroups per space (at most)
 constexpr int FIN_ROWS_MIN = 512;  // rows per workgroup (at least)
-constexpr int FIN_RR = 64;         // R^2 for R <= 8
+constexpr int FIN_RR = 256;        // R^2 for R <= 16
 
 struct FinRows {
   int g, ng, r0, r1;
@@ -708,6 +735,176 @@ __global__ void __launch_bounds__(WT) fin4_kernel(WhitenSpace a0, WhitenSpace a1
   if (f.g == 0 && threadIdx.x < RR) a.cstash[(size_t)m * R + threadIdx.x] = E[threadIdx.x];
 }
 
+// ---- finishing a 16-wide pending block (a group of blocks of 16 columns in all).  The same
+// four launches as fin1_kernel .. fin4_kernel; the 16 x 16 products over the rows (the Gram
+// matrices and E) are taken on the matrix cores: lane (a, g) of a wavefront supplies element
+// (row, a) of the left factor and element (row, b = a) of the right one for rows r + g, and
+// the four wavefronts' tiles are added in order through LDS.  The per-row triangular
+// products that feed them are formed by each lane for its own element.
+constexpr int W16 = 16, L32 = 32, RR16 = 256;
+
+// the workgroup's 16 x 16 tile sums acc (register v of lane a + 16 g holds entry (4 v + g, a))
+// into part[g * FIN_RR + p] (p = row * 16 + column), in a fixed order
+__device__ inline void fin16_write_tile(const wm_d4& acc, double* part, int g, double* red) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, lg = lane >> 4, l16 = lane & 15;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv * RR16 + (4 * v + lg) * W16 + l16] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < RR16) {
+    double t = 0.0;
+    for (int w = 0; w < WT / 64; ++w) t += red[w * RR16 + threadIdx.x];
+    part[(size_t)g * FIN_RR + threadIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(WT) fin1_w16_kernel(WhitenSpace a0, WhitenSpace a1, int s) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  __shared__ double red[(WT / 64) * RR16];
+  const FinRows f = fin_rows(s);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, lg = lane >> 4, l16 = lane & 15;
+  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int base = f.r0 + 4 * wv; base < f.r1; base += 4 * (WT / 64)) {  // uniform per wavefront
+    const int row = base + lg;
+    const double x = row < f.r1 ? a.Z[(size_t)row * L32 + l16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+  }
+  fin16_write_tile(acc, a.fpart, f.g, red);
+}
+
+// y(row, a) = sum_{k <= a} z(row, k) Ri(k, a) for the upper triangular Ri (16 x 16, LDS)
+__device__ inline double fin16_tri(const double* z, const double* Ri, int a) {
+  double t = 0.0;
+  for (int k = 0; k <= a; ++k) t += z[k] * Ri[k * W16 + a];
+  return t;
+}
+
+__global__ void __launch_bounds__(WT) fin2_w16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int step) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  __shared__ double red[(WT / 64) * RR16];
+  __shared__ double G[RR16], R1[RR16], R1i[RR16];
+  __shared__ int ok;
+  const FinRows f = fin_rows(s);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, lg = lane >> 4, l16 = lane & 15;
+  fin_sum_partials<RR16>(a.fpart, f.ng, G);
+  if (threadIdx.x == 0) {
+    ok = chol_upper_small(G, R1, W16);
+    if (ok) inv_upper_small(R1, R1i, W16);
+    if (f.g == 0) {  // the outcome and R1 for the next launches
+      a.fstate[0] = ok ? 1.0 : 0.0;
+      for (int p = 0; p < RR16; ++p) a.fstate[8 + p] = ok ? R1[p] : 0.0;
+      if (!ok) atomicMin(a.broken, step);
+    }
+  }
+  __syncthreads();
+  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    // the Gram matrix of P1 = P'' R1^{-1} from the rows as they are, then P1 written back
+    for (int base = f.r0 + 4 * wv; base < f.r1; base += 4 * (WT / 64)) {
+      const int row = base + lg;
+      const double y = row < f.r1 ? fin16_tri(a.Z + (size_t)row * L32, R1i, l16) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(y, y, acc, 0, 0, 0);
+    }
+    __syncthreads();  // every read of this workgroup's rows precedes the writes below
+    for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
+      double* z = a.Z + (size_t)i * L32;
+      double y[W16];
+#pragma unroll
+      for (int c = 0; c < W16; ++c) y[c] = fin16_tri(z, R1i, c);
+#pragma unroll
+      for (int c = 0; c < W16; ++c) z[c] = y[c];
+    }
+  }
+  fin16_write_tile(acc, a.fpart + (size_t)FIN_G * FIN_RR, f.g, red);
+}
+
+__global__ void __launch_bounds__(WT) fin3_w16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m, int step) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  __shared__ double red[(WT / 64) * RR16];
+  __shared__ double G[RR16], R2[RR16], R2i[RR16];
+  __shared__ int ok;
+  const FinRows f = fin_rows(s);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, lg = lane >> 4, l16 = lane & 15;
+  fin_sum_partials<RR16>(a.fpart + (size_t)FIN_G * FIN_RR, f.ng, G);
+  if (threadIdx.x == 0) {
+    ok = a.fstate[0] != 0.0;
+    if (ok) ok = chol_upper_small(G, R2, W16);
+    if (ok) inv_upper_small(R2, R2i, W16);
+    else
+      for (int p = 0; p < RR16; ++p) R2i[p] = 0.0;
+    if (f.g == 0) {
+      if (!ok && a.fstate[0] != 0.0) atomicMin(a.broken, step);
+      a.fstate[1] = ok ? 1.0 : 0.0;
+      for (int u = 0; u < W16; ++u)  // tau = R2 R1 on the diagonal block of T (I after a failure)
+        for (int v = 0; v < W16; ++v) {
+          double t = 0.0;
+          if (ok)
+            for (int k = 0; k < W16; ++k) t += R2[u * W16 + k] * a.fstate[8 + k * W16 + v];
+          else
+            t = (u == v) ? 1.0 : 0.0;
+          a.T[(m + u) + (size_t)(m + v) * a.ldt] = (u <= v) ? t : 0.0;
+        }
+    }
+  }
+  __syncthreads();
+  // E = q^T w' with q = P1 R2^{-1} from the rows as they are, then q written to Q and Z
+  wm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int base = f.r0 + 4 * wv; base < f.r1; base += 4 * (WT / 64)) {
+    const int row = base + lg;
+    const bool rok = row < f.r1;
+    const double* z = a.Z + (size_t)(rok ? row : f.r0) * L32;
+    const double q = rok ? fin16_tri(z, R2i, l16) : 0.0;
+    const double w = rok ? z[W16 + l16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(q, w, acc, 0, 0, 0);
+  }
+  __syncthreads();  // every read of this workgroup's rows precedes the writes below
+  for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
+    double* z = a.Z + (size_t)i * L32;
+    double q[W16];
+#pragma unroll
+    for (int c = 0; c < W16; ++c) q[c] = fin16_tri(z, R2i, c);
+#pragma unroll
+    for (int c = 0; c < W16; ++c) {
+      a.Q[(size_t)(m + c) * s + i] = q[c];
+      z[c] = q[c];
+    }
+  }
+  fin16_write_tile(acc, a.fpart + (size_t)2 * FIN_G * FIN_RR, f.g, red);
+}
+
+__global__ void __launch_bounds__(WT) fin4_w16_kernel(WhitenSpace a0, WhitenSpace a1, int s, int m) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  __shared__ double E[RR16];
+  const FinRows f = fin_rows(s);
+  fin_sum_partials<RR16>(a.fpart + (size_t)2 * FIN_G * FIN_RR, f.ng, E);
+  for (int i = f.r0 + threadIdx.x; i < f.r1; i += WT) {
+    double* z = a.Z + (size_t)i * L32;
+    double q[W16], v[W16];
+#pragma unroll
+    for (int x = 0; x < W16; ++x) {
+      q[x] = z[x];
+      v[x] = z[W16 + x];
+    }
+#pragma unroll 1
+    for (int x = 0; x < W16; ++x) {  // v -= q(x) E(x, :), one row of E at a time
+      const double qx = q[x];
+#pragma unroll
+      for (int y = 0; y < W16; ++y) v[y] -= qx * E[x * W16 + y];
+    }
+#pragma unroll
+    for (int y = 0; y < W16; ++y) z[y] = v[y];
+  }
+  // T column block of the finished block and the pending block's coefficients [b; E],
+  // the 16 m entries split over the workgroups
+  const int tot = m * W16, per = (tot + f.ng - 1) / f.ng, e0 = f.g * per, e1 = min(tot, e0 + per);
+  for (int e = e0 + threadIdx.x; e < e1; e += WT) {
+    const int j = e / W16, c = e % W16;
+    const double* czj = a.cz + (size_t)j * L32;
+    a.T[j + (size_t)(m + c) * a.ldt] = a.cstash[e] + czj[c];
+    a.cstash[e] = czj[W16 + c];
+  }
+  if (f.g == 0 && threadIdx.x < RR16) a.cstash[(size_t)m * W16 + threadIdx.x] = E[threadIdx.x];
+}
+
 }  // namespace
 
 size_t whiten_fin_doubles() { return (size_t)3 * FIN_G * FIN_RR; }
@@ -776,22 +973,35 @@ namespace {
 template <int R>
 void sweep_pair(int s, int m, int pass, const WhitenSpace& a, const WhitenSpace& b, int ns, hipStream_t st) {
   const int nchunk = ceil_div(s, QT_ROWS);
-  // the matrix-core sweeps read Q in 16-byte pairs of rows: an even s keeps them aligned
-  const bool mfma = R == 16 && s % 2 == 0;
-  if (mfma) {
-    hipLaunchKernelGGL(qtw_mfma16_kernel, dim3(ceil_div(m, (WT / 64) * 16), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
-  } else {
-    const int tile = (WT / 64) * qt_cols<R>();
-    hipLaunchKernelGGL((qtw_split_kernel<R>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+  // R = 16, 32: the matrix-core sweeps (they read Q in 16-byte pairs of rows: an even s keeps
+  // them aligned; 32-wide blocks are only formed for even s); other widths: the vector sweeps
+  bool mfma = false;
+  if constexpr (R == 16 || R == 32) {
+    constexpr int NT = R / 16;
+    mfma = s % 2 == 0;
+    SKR_REQUIRE(mfma || R == 16, "32-wide sweeps need an even number of sketch rows");
+    if (mfma)
+      hipLaunchKernelGGL((qtw_mfma_kernel<NT>), dim3(ceil_div(m, (WT / 64) * 16), nchunk, ns), dim3(WT), 0, st, a, b,
+                         s, m);
+  }
+  if constexpr (R <= 16) {
+    if (!mfma) {
+      const int tile = (WT / 64) * qt_cols<R>();
+      hipLaunchKernelGGL((qtw_split_kernel<R>), dim3(ceil_div(m, tile), nchunk, ns), dim3(WT), 0, st, a, b, s, m);
+    }
   }
   check_launch("whiten_qtw");
   hipLaunchKernelGGL(qtw_sum_kernel, dim3(std::min(1024, ceil_div((int64_t)m * R, 256)), ns), dim3(256), 0, st, a, b,
                      m, R, nchunk, pass);
   check_launch("whiten_qtw_sum");
-  if (mfma)
-    hipLaunchKernelGGL(qc_mfma16_kernel, dim3(ceil_div(s, (WT / 64) * 16), ns), dim3(WT), 0, st, a, b, s, m, pass);
-  else
-    hipLaunchKernelGGL((qc_rows_kernel<R>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s, m, pass);
+  if constexpr (R == 16 || R == 32) {
+    if (mfma)
+      hipLaunchKernelGGL((qc_mfma_kernel<R / 16>), dim3(ceil_div(s, (WT / 64) * 16), ns), dim3(WT), 0, st, a, b, s, m,
+                         pass);
+  }
+  if constexpr (R <= 16) {
+    if (!mfma) hipLaunchKernelGGL((qc_rows_kernel<R>), dim3(ceil_div(s, QC_ROWS), ns), dim3(WT), 0, st, a, b, s, m, pass);
+  }
   check_launch("whiten_qc");
 }
 
@@ -813,7 +1023,8 @@ void finish_block(int r, int s, int m, int step, const WhitenSpace& a, const Whi
 
 void launch_whiten_delayed(int r, int s, int m, int step, int mode, const WhitenSpace& a, const WhitenSpace& b,
                            hipStream_t st, int nspaces) {
-  SKR_REQUIRE(whiten_delayed_supported(r), "delayed re-orthogonalisation needs r <= 8");
+  SKR_REQUIRE(whiten_delayed_supported(r) || (r == W16 && s % 2 == 0),
+              "delayed re-orthogonalisation needs r <= 8, or 16 with an even s");
   SKR_REQUIRE(m >= 1, "delayed re-orthogonalisation needs a finished first block");
   const int ns = nspaces == 1 ? 1 : 2;
   const int mv = std::max(1, std::min(2048, ceil_div((int64_t)s * r, 256)));
@@ -841,15 +1052,23 @@ void launch_whiten_delayed(int r, int s, int m, int step, int mode, const Whiten
       case 5: sweep_pair<10>(s, m, 0, a2, b2, ns, st); break;
       case 6: sweep_pair<12>(s, m, 0, a2, b2, ns, st); break;
       case 7: sweep_pair<14>(s, m, 0, a2, b2, ns, st); break;
-      default: sweep_pair<16>(s, m, 0, a2, b2, ns, st); break;
+      case 8: sweep_pair<16>(s, m, 0, a2, b2, ns, st); break;
+      default: sweep_pair<32>(s, m, 0, a2, b2, ns, st); break;
     }
     const dim3 fg(fin_groups(s), ns);
-    WH_DISPATCH(r, {
-      hipLaunchKernelGGL((fin1_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s);
-      hipLaunchKernelGGL((fin2_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, step);
-      hipLaunchKernelGGL((fin3_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m, step);
-      hipLaunchKernelGGL((fin4_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m);
-    });
+    if (r == W16) {
+      hipLaunchKernelGGL(fin1_w16_kernel, fg, dim3(WT), 0, st, a, b, s);
+      hipLaunchKernelGGL(fin2_w16_kernel, fg, dim3(WT), 0, st, a, b, s, step);
+      hipLaunchKernelGGL(fin3_w16_kernel, fg, dim3(WT), 0, st, a, b, s, m, step);
+      hipLaunchKernelGGL(fin4_w16_kernel, fg, dim3(WT), 0, st, a, b, s, m);
+    } else {
+      WH_DISPATCH(r, {
+        hipLaunchKernelGGL((fin1_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s);
+        hipLaunchKernelGGL((fin2_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, step);
+        hipLaunchKernelGGL((fin3_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m, step);
+        hipLaunchKernelGGL((fin4_kernel<RR_>), fg, dim3(WT), 0, st, a, b, s, m);
+      });
+    }
     check_launch("whiten_finish_delayed");
   } else {
     SKR_REQUIRE(mode == WHITEN_FLUSH, "unknown whitening mode");
