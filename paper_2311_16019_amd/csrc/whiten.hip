@@ -905,6 +905,14 @@ __global__ void __launch_bounds__(WT) fin4_w16_kernel(WhitenSpace a0, WhitenSpac
   if (f.g == 0 && threadIdx.x < RR16) a.cstash[(size_t)m * W16 + threadIdx.x] = E[threadIdx.x];
 }
 
+// T(0 : m, m : m + R) = c1 + c2 (the first- and second-pass coefficients of a flushed block)
+__global__ void tcol_kernel(WhitenSpace a0, WhitenSpace a1, int m, int R) {
+  const WhitenSpace& a = blockIdx.y ? a1 : a0;
+  const int total = m * R;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x)
+    a.T[(e / R) + (size_t)(m + e % R) * a.ldt] = a.c1[e] + a.c2[e];
+}
+
 }  // namespace
 
 size_t whiten_fin_doubles() { return (size_t)3 * FIN_G * FIN_RR; }
@@ -1084,7 +1092,18 @@ void launch_whiten_delayed(int r, int s, int m, int step, int mode, const Whiten
     a2.c2 = a.cz;
     b2.c2 = b.cz;
     WH_DISPATCH(r, sweep_pair<RR_>(s, m, 1, a2, b2, ns, st));
-    finish_block(r, s, m, step, a2, b2, ns, st);
+    if (r == W16) {  // the multi-workgroup finish of a 16-wide block, back in Z[:, 0 : 16]
+      hipLaunchKernelGGL(dcgs_move_kernel, dim3(mv, ns), dim3(256), 0, st, a2, b2, s, r, 2);
+      const dim3 fg(fin_groups(s), ns);
+      hipLaunchKernelGGL(fin1_w16_kernel, fg, dim3(WT), 0, st, a, b, s);
+      hipLaunchKernelGGL(fin2_w16_kernel, fg, dim3(WT), 0, st, a, b, s, step);
+      hipLaunchKernelGGL(fin3_w16_kernel, fg, dim3(WT), 0, st, a, b, s, m, step);
+      hipLaunchKernelGGL(tcol_kernel, dim3(std::max(1, std::min(1024, ceil_div((int64_t)m * r, 256))), ns), dim3(256),
+                         0, st, a2, b2, m, r);
+      check_launch("whiten_flush_w16");
+    } else {
+      finish_block(r, s, m, step, a2, b2, ns, st);
+    }
   }
 }
 
