@@ -5,7 +5,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libskrylov.so")
+# SKR_LIBRARY selects another build of the library (the host-sanitizer build, for instance)
+LIB_PATH = os.environ.get("SKR_LIBRARY") or os.path.join(_HERE, "libskrylov.so")
 
 SKR_OK, SKR_NOT_CONVERGED, SKR_BREAKDOWN = 0, 1, 2
 SKR_EINVAL, SKR_EHIP, SKR_ENOMEM, SKR_ENOTSUP, SKR_EPROJ = -1, -2, -3, -4, -5
