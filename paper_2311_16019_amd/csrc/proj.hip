@@ -36,6 +36,10 @@ __global__ void set_scalar_kernel(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+__global__ void copy_scalar_kernel(const double* src, double* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 // Frobenius-norm scaling of the sign iteration, mu = (||Z^{-1}||_F / ||Z||_F)^(1/2) with the
 // diagonal blocks of Z = [[A, C], [0, -B]] standing in for Z (the coupling block C does not
 // enter the spectrum); mu = 1 once the iteration is in its quadratic phase.
@@ -462,9 +466,14 @@ ProjSolver::ProjSolver(int r, int mmax, hipStream_t st) : r_(r), mmax_(mmax), st
   info_.alloc(2 + QMAX);  // [rank loss, Schur, one per shifted solve]
   scal_.alloc(SCAL_N);
   scratch_.alloc(dense::scratch_doubles());
+  cscal_.alloc(3);
+  cscratch_.alloc(dense::scratch_doubles());
   aux_ = stream_acquire();
+  cst_ = stream_acquire();
   SKR_HIP(hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming));
   SKR_HIP(hipEventCreateWithFlags(&ev_aux_, hipEventDisableTiming));
+  SKR_HIP(hipEventCreateWithFlags(&ev_cin_, hipEventDisableTiming));
+  SKR_HIP(hipEventCreateWithFlags(&ev_c_, hipEventDisableTiming));
   for (auto& d : dst_) d = stream_acquire();
   for (auto& e : dev_) SKR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -475,9 +484,13 @@ ProjSolver::~ProjSolver() {
   for (auto e : dev_)
     if (e) (void)hipEventDestroy(e);
   if (aux_) (void)hipStreamSynchronize(aux_);
+  if (cst_) (void)hipStreamSynchronize(cst_);
   if (ev_main_) (void)hipEventDestroy(ev_main_);
   if (ev_aux_) (void)hipEventDestroy(ev_aux_);
+  if (ev_cin_) (void)hipEventDestroy(ev_cin_);
+  if (ev_c_) (void)hipEventDestroy(ev_c_);
   if (aux_) stream_release(aux_);
+  if (cst_) stream_release(cst_);
 }
 
 void ProjSolver::form(int d, const ProjSpace& sp, double* Mbar, hipStream_t st) {
@@ -657,6 +670,7 @@ void ProjSolver::deflate_right(int m, const double* Al, int lal, const double* M
 void ProjSolver::quiesce() {
   (void)hipStreamSynchronize(st_);
   if (aux_) (void)hipStreamSynchronize(aux_);
+  if (cst_) (void)hipStreamSynchronize(cst_);
   for (auto s : dst_)
     if (s) (void)hipStreamSynchronize(s);
 }
@@ -717,6 +731,9 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       const dense::GjJob jobs[2] = {{m, m, lu_.p, m, gjw_a_.p, gjd_a_.p, info_.p, nullptr, st_},
                                     {m, m, lub_.p, m, gjw_b_.p, gjd_b_.p, info_.p + 1, nullptr, aux_}};
       dense::gj_eliminate_many(jobs, lyap_ ? 1 : 2);
+      // the inverses overwrite what the previous step's product for C still reads
+      SKR_HIP(hipStreamWaitEvent(aux_, ev_c_, 0));
+      SKR_HIP(hipStreamWaitEvent(st_, ev_c_, 0));
       if (!lyap_) dense::gj_inverse(m, lub_.p, m, gjw_b_.p, bi_.p, m, aux_);
       SKR_HIP(hipEventRecord(ev_aux_, aux_));
       dense::gj_inverse(m, lu_.p, m, gjw_a_.p, ai_.p, m, st_);
@@ -730,9 +747,22 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       }
       hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, scale ? 1 : 0);
       check_launch("mu");
-      dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, st_);
-      dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, st_);
+      // C_{k+1} = (mu C + mu^{-1} A^{-1} C B^{-1}) / 2 on a stream of its own: the host's
+      // decision needs only A_{k+1} and B_{k+1}, so the two products for C overlap the next
+      // step's elimination chains (whose inverses wait for them)
+      hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, cscal_.p);
+      check_launch("copy_scalar");
+      SKR_HIP(hipEventRecord(ev_cin_, st_));
+      SKR_HIP(hipStreamWaitEvent(cst_, ev_cin_, 0));
+      dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, cst_);
+      dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, cst_);
+      dense::newton_combine(m, m, cscal_.p, c_.p, m, w2_.p, m, c_.p, m, cscal_.p + 1, cscal_.p + 2, nullptr,
+                            cscratch_.p, cst_);
+      SKR_HIP(hipEventRecord(ev_c_, cst_));
     } else {
+      // the products below overwrite what the last exact step's product for C still reads
+      SKR_HIP(hipStreamWaitEvent(aux_, ev_c_, 0));
+      SKR_HIP(hipStreamWaitEvent(st_, ev_c_, 0));
       // B^2 -> lub_, B^{-1} ~ 2B - B B^2 -> bi_ on the auxiliary stream
       if (!lyap_) {
         dense::gemm(false, false, m, m, m, 1.0, b_.p, m, b_.p, m, 0.0, lub_.p, m, aux_);
@@ -757,8 +787,8 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       dense::gemm(false, false, m, m, m, -1.0, c_.p, m, lub_.p, m, 1.0, w2_.p, m, st_);
       hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, 1.0);
       check_launch("set_scalar");
+      dense::newton_combine(m, m, s + MU, c_.p, m, w2_.p, m, c_.p, m, s + DC, s + NC, nullptr, scratch_.p, st_);
     }
-    dense::newton_combine(m, m, s + MU, c_.p, m, w2_.p, m, c_.p, m, s + DC, s + NC, nullptr, scratch_.p, st_);
     dense::newton_combine(m, m, s + MU, a_.p, m, ai_.p, m, a_.p, m, s + DA, s + NA, s + TA, scratch_.p, st_);
     dense::newton_combine(m, m, s + MU, b_.p, m, bi_.p, m, b_.p, m, s + DB, s + NB_, s + TB, scratch_.p, st_);
     SKR_HIP(hipMemcpyAsync(hs.data(), s, SCAL_N * sizeof(double), hipMemcpyDeviceToHost, st_));
@@ -784,6 +814,7 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     }
     prev = rel;
   }
+  SKR_HIP(hipStreamWaitEvent(st_, ev_c_, 0));  // C of the last exact step
   const int qa = (int)std::lround((m - hs[TA]) / 2.0), qb = (int)std::lround((m - hs[TB]) / 2.0);
   if (stats) {
     if (pass == 0) stats->newton_iters = it;

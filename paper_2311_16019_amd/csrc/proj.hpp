@@ -65,12 +65,14 @@ class ProjSolver {
   bool lyap_ = false;
   hipStream_t st_;
   hipStream_t aux_ = nullptr;  // second stream: the two inversions of a Newton step overlap
-  hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr;
+  hipStream_t cst_ = nullptr;  // third stream: the products for C overlap the next step's eliminations
+  hipEvent_t ev_main_ = nullptr, ev_aux_ = nullptr, ev_cin_ = nullptr, ev_c_ = nullptr;
   DBuf<double> lub_;
   DBuf<double> mbar_u_, mbar_v_, a_, b_, ai_, bi_, c_, w1_, w2_, lu_, y1_, y2_;
   DBuf<int> gjw_a_, gjw_b_, info_;
   DBuf<double> gjd_a_, gjd_b_;
   DBuf<double> scal_, scratch_;
+  DBuf<double> cscal_, cscratch_;  // mu, change and norm of the C update on its own stream
   DBuf<double> acapart_, dws_, kbuf_;
   // deflated shifted solves: DEFL_NS eliminations at a time, one stream each
   static constexpr int DEFL_NS = 4;
