@@ -342,23 +342,22 @@ __global__ void __launch_bounds__(WG) cgs_pass2_kernel(CgsPass<T> s0, CgsPass<T>
 constexpr int CGS_GROUP = 4;
 
 // Pass 1b for nw > 3 window blocks: the products U'_i^T U~ in groups of CGS_GROUP blocks,
-// one pass over the workgroup's rows per group (U~ is read once per group, each window
-// block once), U~^T U~ in the first group's pass; partials in the layout of
-// cgs_dots_kernel.
+// one wavefront per group over all of the workgroup's rows (the group wavefronts read the
+// same rows of U~ at about the same time, so U~ comes from HBM once: a pass per group over
+// the rows re-read it from HBM, 128 MB per step at n = 1e6, r = 4, k = 10), and U~^T U~ in
+// the workgroup's last wavefront; each wavefront's totals are its workgroup's partials, in
+// the layout of cgs_dots_kernel.
+static_assert(CGS_KMAX <= CGS_GROUP * (WG / 64 - 1), "a wavefront per window group and one for U~^T U~");
+
 template <typename T, int R>
 __global__ void __launch_bounds__(WG) cgs_dots_wide_kernel(CgsPass<T> s0, CgsPass<T> s1, int nw) {
   constexpr int RR = R * R, NG = R * (R + 1) / 2, GV = CGS_GROUP * RR;
   const Rows wi = rows_of(s0, s1);
   const CgsPass<T>& sp = wi.space ? s1 : s0;
-  __shared__ double scratch[(WG / 64) * GV];
-  double accg[NG];
-#pragma unroll
-  for (int v = 0; v < NG; ++v) accg[v] = 0.0;
-  for (int g0 = 0; g0 < nw; g0 += CGS_GROUP) {
-    const int ng = min(CGS_GROUP, nw - g0);
-    double accw[GV];
-#pragma unroll
-    for (int v = 0; v < GV; ++v) accw[v] = 0.0;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;  // wv is uniform over the wavefront
+  const int ngroups = (nw + CGS_GROUP - 1) / CGS_GROUP;
+  if (wv < ngroups) {
+    const int g0 = wv * CGS_GROUP, ng = min(CGS_GROUP, nw - g0);
     // the group's block pointers, selected with constant indices (a run-time index into the
     // kernel argument would move the argument structure to scratch memory)
     const T* wp[CGS_GROUP];
@@ -369,19 +368,15 @@ __global__ void __launch_bounds__(WG) cgs_dots_wide_kernel(CgsPass<T> s0, CgsPas
       for (int t = 0; t < KM; ++t)
         if (t == g0 + i) wp[i] = sp.W[t];
     }
-    for (int row = wi.row0 + threadIdx.x; row < wi.row1; row += WG) {
+    double accw[GV];
+#pragma unroll
+    for (int v = 0; v < GV; ++v) accw[v] = 0.0;
+    for (int row = wi.row0 + lane; row < wi.row1; row += 64) {
       T y[R], w[CGS_GROUP][R];
       load_raw<T, R>(sp.Y, row, y);
 #pragma unroll
       for (int i = 0; i < CGS_GROUP; ++i)
         if (i < ng) load_raw<T, R>(wp[i], row, w[i]);
-      if (g0 == 0) {
-        int g = 0;
-#pragma unroll
-        for (int a = 0; a < R; ++a)
-#pragma unroll
-          for (int b = a; b < R; ++b, ++g) accg[g] += (double)y[a] * (double)y[b];
-      }
 #pragma unroll
       for (int i = 0; i < CGS_GROUP; ++i)
         if (i < ng)
@@ -391,11 +386,23 @@ __global__ void __launch_bounds__(WG) cgs_dots_wide_kernel(CgsPass<T> s0, CgsPas
             for (int b = 0; b < R; ++b) accw[i * RR + a * R + b] += (double)w[i][a] * (double)y[b];
     }
     // this group's values are window values g0 * RR .. (g0 + ng) * RR (value-major partials)
-    write_partials<GV>(accw, sp.part + (size_t)g0 * RR * sp.nwg, sp.nwg, wi.local, scratch, ng * RR);
-    __syncthreads();  // scratch is reused by the next group
-  }
-  double acc[RR];
-  {
+    int idx;
+    const double t = wave_transpose_sum<GV>(accw, idx);
+    if (idx >= 0 && idx < ng * RR) sp.part[(size_t)(g0 * RR + idx) * sp.nwg + wi.local] = t;
+  } else if (wv == WG / 64 - 1) {
+    double accg[NG];
+#pragma unroll
+    for (int v = 0; v < NG; ++v) accg[v] = 0.0;
+    for (int row = wi.row0 + lane; row < wi.row1; row += 64) {
+      T y[R];
+      load_raw<T, R>(sp.Y, row, y);
+      int g = 0;
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = a; b < R; ++b, ++g) accg[g] += (double)y[a] * (double)y[b];
+    }
+    double acc[RR];
     int g = 0;
 #pragma unroll
     for (int a = 0; a < R; ++a)
@@ -404,8 +411,10 @@ __global__ void __launch_bounds__(WG) cgs_dots_wide_kernel(CgsPass<T> s0, CgsPas
         acc[a * R + b] = accg[g];
         acc[b * R + a] = accg[g];
       }
+    int idx;
+    const double t = wave_transpose_sum<RR>(acc, idx);
+    if (idx >= 0) sp.part[(size_t)(nw * RR + idx) * sp.nwg + wi.local] = t;
   }
-  write_partials<RR>(acc, sp.part + (size_t)nw * RR * sp.nwg, sp.nwg, wi.local, scratch);
 }
 
 // Pass 2 for nw > 3 window blocks: U' = (U~ - W D) R1^{-1} with all window rows of a row in
