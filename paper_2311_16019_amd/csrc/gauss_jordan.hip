@@ -126,7 +126,7 @@ constexpr bool gj_stage() { return TG * RPT * NB * 8 <= 128 * 1024; }
 // TG threads per workgroup (one or two wavefronts per SIMD); the previous panel's columns
 // are staged in LDS when they fit (STAGE), else read from global memory (L2) column by column.
 template <int RPT, int NB, int TG>
-__device__ void panel_workgroup(const GjArgs& g, double* sl) {
+__device__ __forceinline__ void panel_workgroup(const GjArgs& g, double* sl) {
   __shared__ int pl[NB];
   __shared__ int pivl[NB];
   __shared__ double amat[NB][NB];
@@ -178,13 +178,15 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     }
   }
   double x[RPT][NB];
-  bool elig[RPT];
+  // bit q: row_of(q) may still pivot (a bit mask in one register rather than RPT lane masks)
+  using Mask = std::conditional_t<(RPT > 32), uint64_t, uint32_t>;
+  Mask elig = 0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int row = row_of<RPT, TG>(q);
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[q][c] = (row < g.n && c < nbc) ? g.S[row + (size_t)(k0 + c) * g.ld] : 0.0;
-    elig[q] = (row < g.n) && (g.used[row] == 0);
+    if (row < g.n && g.used[row] == 0) elig |= Mask(1) << q;
   }
   if (g.b > 0) {  // the previous panel applied to this panel's columns
     if (tid < NB) pl[tid] = g.piv[kp0 + tid];
@@ -237,7 +239,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
     Key key = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const Key kq = elig[q] ? pivot_key(fabs(x[q][c]), row_of<RPT, TG>(q), Key{}) : Key{0};
+      const Key kq = ((elig >> q) & 1) ? pivot_key(fabs(x[q][c]), row_of<RPT, TG>(q), Key{}) : Key{0};
       key = kq > key ? kq : key;
     }
     const Key wkey = wave_max_key(key);  // uniform over the wavefront
@@ -288,7 +290,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
         if (q == gq) {
 #pragma unroll
           for (int cc = 0; cc < NB; ++cc) x[q][cc] = (cc == c) ? inv : ps[cc];
-          elig[q] = false;
+          elig &= ~(Mask(1) << q);
         }
     }
     if (tid == 0) {
@@ -319,7 +321,7 @@ __device__ void panel_workgroup(const GjArgs& g, double* sl) {
 // Update workgroup of launch b >= 1: apply E_{b-1} to its strips of columns outside
 // K_{b-1} and K_b.
 template <int RPT, int NB, int TG>
-__device__ void update_workgroup(const GjArgs& g) {
+__device__ __forceinline__ void update_workgroup(const GjArgs& g) {
   __shared__ int pl[NB];
   __shared__ double am[NB][GJ_CW];
   const int tid = threadIdx.x;
