@@ -181,12 +181,26 @@ __device__ __forceinline__ void panel_workgroup(const GjArgs& g, double* sl) {
   // bit q: row_of(q) may still pivot (a bit mask in one register rather than RPT lane masks)
   using Mask = std::conditional_t<(RPT > 32), uint64_t, uint32_t>;
   Mask elig = 0;
+  {
+    // Every lane loads (row and column clamped into the panel, the extra values zeroed
+    // afterwards), so that all loads are in flight together: conditional loads became
+    // branches with a wait for each row's flag before the next row's loads.
+    int usedv[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int row = row_of<RPT, TG>(q);
+    for (int q = 0; q < RPT; ++q) {
+      const int rc = min(row_of<RPT, TG>(q), g.n - 1);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) x[q][c] = (row < g.n && c < nbc) ? g.S[row + (size_t)(k0 + c) * g.ld] : 0.0;
-    if (row < g.n && g.used[row] == 0) elig |= Mask(1) << q;
+      for (int c = 0; c < NB; ++c) x[q][c] = g.S[rc + (size_t)(k0 + min(c, nbc - 1)) * g.ld];
+      usedv[q] = g.used[rc];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const bool in = row_of<RPT, TG>(q) < g.n;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (!in || c >= nbc) x[q][c] = 0.0;
+      if (in && usedv[q] == 0) elig |= Mask(1) << q;
+    }
   }
   if (g.b > 0) {  // the previous panel applied to this panel's columns
     if (tid < NB) pl[tid] = g.piv[kp0 + tid];
@@ -214,7 +228,7 @@ __device__ __forceinline__ void panel_workgroup(const GjArgs& g, double* sl) {
       } else {  // column t of the previous panel, written by the previous launch (in L2)
         const double* col = g.S + (size_t)(kp0 + t) * g.ld;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) sv[q] = (row_of<RPT, TG>(q) < g.n) ? col[row_of<RPT, TG>(q)] : 0.0;
+        for (int q = 0; q < RPT; ++q) sv[q] = col[min(row_of<RPT, TG>(q), g.n - 1)];  // rows past n: unused
       }
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
@@ -331,12 +345,19 @@ __device__ __forceinline__ void update_workgroup(const GjArgs& g) {
   __syncthreads();
   double s[RPT][NB];
   int tp[RPT];
+  // clamped, unconditional loads (all in flight together), zeroed afterwards
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int rc = min(row_of<RPT, TG>(q), g.n - 1);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) s[q][t] = g.S[rc + (size_t)(kp0 + min(t, nbp - 1)) * g.ld];
+  }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int row = row_of<RPT, TG>(q);
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      s[q][t] = (row < g.n && t < nbp) ? g.S[row + (size_t)(kp0 + t) * g.ld] : 0.0;
+      if (row >= g.n || t >= nbp) s[q][t] = 0.0;
     tp[q] = -1;
     for (int t = 0; t < nbp; ++t)
       if (pl[t] == row) tp[q] = t;
@@ -359,7 +380,7 @@ __device__ __forceinline__ void update_workgroup(const GjArgs& g) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         acc[q] = 0.0;
-        v[q] = (row_of<RPT, TG>(q) < g.n) ? col[row_of<RPT, TG>(q)] : 0.0;
+        v[q] = col[min(row_of<RPT, TG>(q), g.n - 1)];  // rows past n are not stored
       }
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
@@ -569,6 +590,7 @@ void plan_elimination(const GjJob& j, GjPlan& plan, std::vector<std::unique_ptr<
   else if (n <= 1024) SKR_GJ_PLAN(4, 16, 256);
   else if (n <= 2048) SKR_GJ_PLAN(4, 16, 512);
   else if (n <= 4096) SKR_GJ_PLAN(8, 8, 512);
+  else if (n <= 6144) SKR_GJ_PLAN(12, 4, 512);  // no register spills, unlike 16 rows per thread
   else if (n <= 8192) SKR_GJ_PLAN(16, 4, 512);
   else SKR_GJ_PLAN(64, 1, 256);
 #undef SKR_GJ_PLAN
