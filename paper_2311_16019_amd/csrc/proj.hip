@@ -56,6 +56,24 @@ __global__ void rhs_kernel(int m, int r, const double* F11, double* F) {
   }
 }
 
+// F = E_r F11 E_r^T in factored form L R^T (m x r each): L = E_r, R = E_r F11^T.
+__global__ void frhs_kernel(int m, int r, const double* F11, double* L, double* R) {
+  const size_t total = (size_t)m * r;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), t = (int)(e / m);
+    L[e] = (i == t) ? 1.0 : 0.0;
+    R[e] = (i < r) ? F11[t * r + i] : 0.0;
+  }
+}
+
+// The right factor of a factored Newton step for C: its first mq entries (the old columns)
+// scaled by mu / 2, the next mq (B^{-T} R) by 1 / (2 mu).
+__global__ void fscale_kernel(size_t mq, const double* mu_dev, double* R) {
+  const double mu = *mu_dev, lo = 0.5 * mu, hi = 0.5 / mu;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * mq; e += (size_t)gridDim.x * blockDim.x)
+    R[e] *= (e < mq) ? lo : hi;
+}
+
 // rho^2 = ||hh Y[m-r:m, :]||_F^2 + ||Y[:, m-r:m] gh^T||_F^2, hh/gh r x r column-major with ld.
 // out[0] = ||hh Y(m-r:m, :)||_F^2, out[1] = ||Y(:, m-r:m) gh^T||_F^2
 __global__ void rho_kernel(int m, int r, const double* Y, const double* hh, int ldh, const double* gh, int ldg,
@@ -699,10 +717,21 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
   for (int pass = 0; pass < 2; ++pass) {
   dense::copy(m, m, mbar_u_.p, ldm, a_.p, m, st_);
   dense::transpose(m, m, mbar_v_.p, ldm, b_.p, m, st_);
+  // While the right-hand side is the rank-r F (pass 0), C is kept in factored form C = L R^T
+  // (L in w1_, R in w2_, q columns each): an exact step appends A^{-1} L to L and B^{-T} R to
+  // R, two products with q columns instead of two with m.  No truncation: the rank doubles
+  // every step, and C is formed once 2q would pass m / 2, before a Newton-Schulz step and
+  // after the iteration.
+  bool fac = (pass == 0);
+  int q = r_;
+  auto form_c = [&]() {
+    dense::gemm(false, true, m, m, q, 1.0, w1_.p, m, w2_.p, m, 0.0, c_.p, m, st_);
+    fac = false;
+  };
   if (pass == 0) {
-    hipLaunchKernelGGL(rhs_kernel, dim3(std::min(4096, ceil_div((int64_t)m * m, 256))), dim3(256), 0, st_, m, r_, F11,
-                       c_.p);
-    check_launch("rhs");
+    hipLaunchKernelGGL(frhs_kernel, dim3(std::max(1, std::min(4096, ceil_div((int64_t)m * r_, 256)))), dim3(256), 0,
+                       st_, m, r_, F11, w1_.p, w2_.p);
+    check_launch("frhs");
   } else {  // Y -> y1_ (free until the factorisation); c = R = -(M_A Y + Y M_B^T - F), left in w1_
     if (!y1_.p) { y1_.alloc((size_t)mmax_ * mmax_); y2_.alloc((size_t)mmax_ * mmax_); }
     dense::copy(m, m, c_.p, m, y1_.p, m, st_);
@@ -747,19 +776,37 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       }
       hipLaunchKernelGGL(mu_kernel, dim3(1), dim3(1), 0, st_, s, scale ? 1 : 0);
       check_launch("mu");
-      // C_{k+1} = (mu C + mu^{-1} A^{-1} C B^{-1}) / 2 on a stream of its own: the host's
-      // decision needs only A_{k+1} and B_{k+1}, so the two products for C overlap the next
-      // step's elimination chains (whose inverses wait for them)
       hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, cscal_.p);
       check_launch("copy_scalar");
-      SKR_HIP(hipEventRecord(ev_cin_, st_));
-      SKR_HIP(hipStreamWaitEvent(cst_, ev_cin_, 0));
-      dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, cst_);
-      dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, cst_);
-      dense::newton_combine(m, m, cscal_.p, c_.p, m, w2_.p, m, c_.p, m, cscal_.p + 1, cscal_.p + 2, nullptr,
-                            cscratch_.p, cst_);
-      SKR_HIP(hipEventRecord(ev_c_, cst_));
+      // A_{k+1} and B_{k+1} first: the host's decision waits for them, and once the products
+      // for C below are running they hold every compute unit
+      dense::newton_combine(m, m, s + MU, a_.p, m, ai_.p, m, a_.p, m, s + DA, s + NA, s + TA, scratch_.p, st_);
+      dense::newton_combine(m, m, s + MU, b_.p, m, bi_.p, m, b_.p, m, s + DB, s + NB_, s + TB, scratch_.p, st_);
+      // C_{k+1} = (mu C + mu^{-1} A^{-1} C B^{-1}) / 2
+      if (fac && 2 * q > m / 2) form_c();
+      if (fac) {
+        // L <- [L, A^{-1} L], R <- [mu R, B^{-T} R / mu] / 2
+        dense::gemm(false, false, m, q, m, 1.0, ai_.p, m, w1_.p, m, 0.0, w1_.p + (size_t)q * m, m, st_);
+        dense::gemm(true, false, m, q, m, 1.0, bi_.p, m, w2_.p, m, 0.0, w2_.p + (size_t)q * m, m, st_);
+        hipLaunchKernelGGL(fscale_kernel, dim3(std::max(1, std::min(4096, ceil_div((int64_t)m * q, 128)))), dim3(256), 0,
+                           st_, (size_t)m * q, s + MU, w2_.p);
+        check_launch("fscale");
+        q *= 2;
+        SKR_HIP(hipEventRecord(ev_c_, st_));
+      } else {
+        // on a stream of its own: the host's decision needs only A_{k+1} and B_{k+1}, so the
+        // two products for C may overlap the next step's elimination chains (whose inverses
+        // wait for them)
+        SKR_HIP(hipEventRecord(ev_cin_, st_));
+        SKR_HIP(hipStreamWaitEvent(cst_, ev_cin_, 0));
+        dense::gemm(false, false, m, m, m, 1.0, ai_.p, m, c_.p, m, 0.0, w1_.p, m, cst_);
+        dense::gemm(false, false, m, m, m, 1.0, w1_.p, m, bi_.p, m, 0.0, w2_.p, m, cst_);
+        dense::newton_combine(m, m, cscal_.p, c_.p, m, w2_.p, m, c_.p, m, cscal_.p + 1, cscal_.p + 2, nullptr,
+                              cscratch_.p, cst_);
+        SKR_HIP(hipEventRecord(ev_c_, cst_));
+      }
     } else {
+      if (fac) form_c();
       // the products below overwrite what the last exact step's product for C still reads
       SKR_HIP(hipStreamWaitEvent(aux_, ev_c_, 0));
       SKR_HIP(hipStreamWaitEvent(st_, ev_c_, 0));
@@ -788,9 +835,9 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
       hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st_, s + MU, 1.0);
       check_launch("set_scalar");
       dense::newton_combine(m, m, s + MU, c_.p, m, w2_.p, m, c_.p, m, s + DC, s + NC, nullptr, scratch_.p, st_);
+      dense::newton_combine(m, m, s + MU, a_.p, m, ai_.p, m, a_.p, m, s + DA, s + NA, s + TA, scratch_.p, st_);
+      dense::newton_combine(m, m, s + MU, b_.p, m, bi_.p, m, b_.p, m, s + DB, s + NB_, s + TB, scratch_.p, st_);
     }
-    dense::newton_combine(m, m, s + MU, a_.p, m, ai_.p, m, a_.p, m, s + DA, s + NA, s + TA, scratch_.p, st_);
-    dense::newton_combine(m, m, s + MU, b_.p, m, bi_.p, m, b_.p, m, s + DB, s + NB_, s + TB, scratch_.p, st_);
     SKR_HIP(hipMemcpyAsync(hs.data(), s, SCAL_N * sizeof(double), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipMemcpyAsync(hinfo, info_.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
     SKR_HIP(hipStreamSynchronize(st_));
@@ -815,6 +862,7 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     prev = rel;
   }
   SKR_HIP(hipStreamWaitEvent(st_, ev_c_, 0));  // C of the last exact step
+  if (fac) form_c();
   const int qa = (int)std::lround((m - hs[TA]) / 2.0), qb = (int)std::lround((m - hs[TB]) / 2.0);
   if (stats) {
     if (pass == 0) stats->newton_iters = it;
