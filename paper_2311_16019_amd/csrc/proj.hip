@@ -120,24 +120,47 @@ __global__ void sub_rhs_kernel(int m, int r, const double* F11, double* W) {
 }
 
 // ---- complete-pivoting low-rank factorisation -------------------------------------
-constexpr int ACA_WG = 256, ACA_G = 512;
+constexpr int ACA_WG = 256, ACA_G = 2048, ACA_UN = 8;
 
-__global__ void aca_update_kernel(int m, double* R, const double* Y1, const double* Y2, const int* state, double* part,
-                                  int* ipart) {
+// The residual update R -= u v^T of the previous cross and the partials of the next pivot
+// search (largest |R(i, j)|, smallest index on ties) and of ||R||_F^2.  Columns across
+// workgroups, rows across threads in batches of ACA_UN with every load issued before the
+// batch is used (indices clamped into the column, the extra entries ignored), so that no
+// index division is needed and a thread visits its entries in increasing order.
+__global__ void __launch_bounds__(ACA_WG) aca_update_kernel(int m, double* R, const double* Y1, const double* Y2,
+                                                            const int* state, double* part, int* ipart) {
   const int k = state[0], done = state[1];
   if (done) return;
   const double* u = k > 0 ? Y1 + (size_t)(k - 1) * m : nullptr;
   const double* v = k > 0 ? Y2 + (size_t)(k - 1) * m : nullptr;
   double best = -1.0, ss = 0.0;
   long long bidx = -1;
-  const size_t total = (size_t)m * m;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    double x = R[e];
-    if (u) { x -= u[i] * v[j]; R[e] = x; }
-    const double ax = fabs(x);
-    ss += x * x;
-    if (ax > best) { best = ax; bidx = (long long)e; }
+  for (int j = blockIdx.x; j < m; j += gridDim.x) {
+    double* col = R + (size_t)j * m;
+    const double vj = u ? v[j] : 0.0;
+    for (int i0 = threadIdx.x; i0 < m; i0 += ACA_WG * ACA_UN) {
+      double x[ACA_UN], uu[ACA_UN];
+#pragma unroll
+      for (int t = 0; t < ACA_UN; ++t) {
+        const int ic = min(i0 + t * ACA_WG, m - 1);
+        x[t] = col[ic];
+        uu[t] = u ? u[ic] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < ACA_UN; ++t) {
+        const int i = i0 + t * ACA_WG;
+        if (i < m) {
+          double xv = x[t];
+          if (u) {
+            xv -= uu[t] * vj;
+            col[i] = xv;
+          }
+          const double ax = fabs(xv);
+          ss += xv * xv;
+          if (ax > best) { best = ax; bidx = (long long)j * m + i; }
+        }
+      }
+    }
   }
   __shared__ double sb[ACA_WG / 64], sss[ACA_WG / 64];
   __shared__ long long si[ACA_WG / 64];
