@@ -874,9 +874,13 @@ double ProjSolver::solve(int d, const ProjSpace& u, const ProjSpace& v, const do
     const double rel = std::sqrt(std::max(hs[DA] / hs[NA], hs[DB] / hs[NB_]));
     if (!std::isfinite(rel))
       throw Error(SKR_EPROJ, "non-finite sign iteration (d = " + std::to_string(d) + ")");
+    const bool unscaled = !scale;  // this step used mu = 1
     if (rel < 1e-2) scale = false;
-    // quadratic convergence: a change below 1e-10 leaves the new iterate at rounding level
-    if (rel < 1e-10) { ++it; break; }
+    // Quadratic convergence: the error of the new iterate is about the square of this step's
+    // change, so an unscaled step whose change is below 1e-8 after one below 1e-3 (the
+    // quadratic phase) leaves it at rounding level; a change below 1e-10 ends the iteration
+    // in any case.
+    if (rel < 1e-10 || (unscaled && prev < 1e-3 && rel < 1e-8)) { ++it; break; }
     if (schulz) {
       if (rel > 0.25 * prev) schulz = false;  // not contracting quadratically: exact inverses again
     } else if (!scale && rel < NS_SWITCH && m <= NS_MAX_M) {
