@@ -33,7 +33,10 @@ constexpr int KM = CGS_KMAX;
 constexpr int CGS_NARROW = 3;
 constexpr int RM = CGS_RMAX;
 constexpr int RR_MAX = RM * RM;
-constexpr int RED_T = 1024;  // threads of the reduce kernels
+constexpr int RED_T = 1024;  // threads of the first reduce kernel
+// Threads of the second: it sums 16 values, and a small workgroup finds a compute unit at
+// once while the whitening's kernels fill the device (1024 threads waited 45 us on average).
+constexpr int RED2_T = 256;
 
 // Layout of CgsSmall::state (doubles).
 struct CgsLayout {
@@ -470,11 +473,12 @@ __global__ void __launch_bounds__(WG) cgs_pass2_wide_kernel(CgsPass<T> s0, CgsPa
 // ------------------------------------------------------------------------- reductions
 // Sum the partials of nv values into out[0..nv): 16 consecutive threads per value (one
 // DPP row), each summing a strided subset of the partials; fixed order throughout.
+template <int NT>
 __device__ inline void sum_partials(const double* part, int nwg, int nv, double* out) {
   const int sub = threadIdx.x % 16;
-  const int nround = (nv + RED_T / 16 - 1) / (RED_T / 16);  // uniform over the workgroup
+  const int nround = (nv + NT / 16 - 1) / (NT / 16);  // uniform over the workgroup
   for (int rd = 0; rd < nround; ++rd) {
-    const int v = threadIdx.x / 16 + rd * (RED_T / 16);
+    const int v = threadIdx.x / 16 + rd * (NT / 16);
     double s = 0.0;
     if (v < nv) {
       const double* p = part + (size_t)v * nwg;
@@ -507,7 +511,7 @@ __global__ void __launch_bounds__(RED_T) cgs_reduce1_kernel(CgsSmall s0, CgsSmal
   __shared__ double D1[LM * RM], D[LM * RM], M1[LM * RM], Z[LM * RM];
   __shared__ double G2[RR_MAX], R1[RR_MAX], R1i[RR_MAX];
   __shared__ double trg0;
-  sum_partials(sm.part, sm.nwg, (nw + 1) * RR, raw);
+  sum_partials<RED_T>(sm.part, sm.nwg, (nw + 1) * RR, raw);
   for (int e = tid; e < nw * RR; e += RED_T) P[e / RR][e % RR] = sm.Pall[(size_t)(i0 + e / RR) * RR + e % RR];
   for (int e = tid; e < m * m; e += RED_T) {
     const int I = e / m, J = e % m, bi = I / r, bj = J / r, a = I % r, b = J % r;
@@ -604,13 +608,13 @@ __global__ void __launch_bounds__(RED_T) cgs_reduce1_kernel(CgsSmall s0, CgsSmal
   if (tid == 0) st[CgsLayout::G0TR] = trg0;
 }
 
-__global__ void __launch_bounds__(RED_T) cgs_reduce2_kernel(CgsSmall s0, CgsSmall s1, int r, int nw, int i0, int d) {
+__global__ void __launch_bounds__(RED2_T) cgs_reduce2_kernel(CgsSmall s0, CgsSmall s1, int r, int nw, int i0, int d) {
   const CgsSmall& sm = blockIdx.x ? s1 : s0;
   const int tid = threadIdx.x, RR = r * r;
   constexpr int LM = KM * RM;
   __shared__ double Gp[RR_MAX], R2[RR_MAX], RF[RR_MAX], R2i[RR_MAX];
   __shared__ int ok_sh;
-  sum_partials(sm.part, sm.nwg, RR, Gp);
+  sum_partials<RED2_T>(sm.part, sm.nwg, RR, Gp);
   __syncthreads();
   const double* st = sm.state;
   if (tid == 0) {
@@ -635,14 +639,14 @@ __global__ void __launch_bounds__(RED_T) cgs_reduce2_kernel(CgsSmall s0, CgsSmal
   __syncthreads();
   const bool ok = ok_sh != 0;
   // h_{d+1,d} = R2 R1 (for the start block: its R factor, ldh = r), P_{d+1}, U'^T U'
-  for (int e = tid; e < RR; e += RED_T) {
+  for (int e = tid; e < RR; e += RED2_T) {
     const int a = e / r, b = e % r;
     sm.H[((size_t)d * r + a) + ((size_t)(d > 0 ? d - 1 : 0) * r + b) * sm.ldh] = RF[e];
     sm.Pall[(size_t)(d + 1) * RR + e] = R2i[e];
     sm.Gall[(size_t)(d + 1) * RR + e] = Gp[e];
   }
   // U'_{i0+i}^T U'_{d+1} = D1raw_i R1^{-1} - sum_j U'_{i0+i}^T U'_{i0+j} C_j
-  for (int e = tid; e < nw * RR; e += RED_T) {
+  for (int e = tid; e < nw * RR; e += RED2_T) {
     const int i = e / RR, a = (e % RR) / r, b = e % r;
     double t = 0.0;
     if (ok) {
@@ -759,7 +763,7 @@ void launch_cgs_reduce1(int r, int nw, int i0, int d, const CgsSmall& a, const C
   check_launch("cgs_reduce1");
 }
 void launch_cgs_reduce2(int r, int nw, int i0, int d, const CgsSmall& a, const CgsSmall& b, hipStream_t st) {
-  hipLaunchKernelGGL(cgs_reduce2_kernel, dim3(2), dim3(RED_T), 0, st, a, b, r, nw, i0, d);
+  hipLaunchKernelGGL(cgs_reduce2_kernel, dim3(2), dim3(RED2_T), 0, st, a, b, r, nw, i0, d);
   check_launch("cgs_reduce2");
 }
 
