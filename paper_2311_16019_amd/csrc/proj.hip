@@ -7,10 +7,11 @@
 //     C_{k+1} = (mu C_k + A_k^{-1} C_k B_k^{-1}/mu)/2,
 // A_k -> sign(M_A), B_k -> sign(M_B^T) and C_k -> 2 Y when both sign limits are the
 // identity (all eigenvalues in the open right half plane, the case of the positive real
-// operators this solver targets).  Every iteration is two Gauss-Jordan inversions and two GEMMs,
-// which map onto the GPU; the paper solves the same equation with Bartels-Stewart (Sec. 6),
-// whose Schur decompositions do not.  Near convergence the inversions are replaced by
-// Newton-Schulz steps (GEMMs only).  When a limit is not the identity the projected matrix
+// operators this solver targets).  Every iteration is two Gauss-Jordan inversions and the
+// products for C (two with q columns while C is kept as L R^T, see solve()), which map onto
+// the GPU; the paper solves the same equation with Bartels-Stewart (Sec. 6), whose Schur
+// decompositions do not.  Near convergence, up to order NS_MAX_M, the inversions are
+// replaced by Newton-Schulz steps (GEMMs only).  When a limit is not the identity the projected matrix
 // is indefinite (the paper's Example 4.5 shows this can happen); the traces of the limits
 // count the eigenvalues in the left half plane, and the part of Y on them is added by a
 // spectral deflation (below).
